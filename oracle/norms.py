@@ -1,0 +1,69 @@
+"""Error norms of a discrete space-time solution (§3.1 eq. norm_V0, §5.1).
+Oracle: test use only.
+
+u_h = sum_i u_i B_i is evaluated on a tensor grid of Gauss points with
+p + 3 points per span (the paper uses element-wise Gauss quadrature without
+stating the count) and compared with an exact solution given by callables.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .assemble import gauss_points, space_index, time_index
+from .bspline import eval_basis_points, num_basis
+from .system import mode_product
+
+
+def _grid(knots, degrees):
+    d = len(knots) - 1
+    pts, wts, mats = [], [], []
+    for k in range(d + 1):
+        x, w = gauss_points(knots[k], degrees[k] + 3)
+        B = eval_basis_points(knots[k], degrees[k], x, nder=2)
+        m = num_basis(knots[k], degrees[k])
+        idx = space_index(m) if k < d else time_index(m)
+        pts.append(x)
+        wts.append(w)
+        mats.append(B[:, :, idx])  # (3, nq, n)
+    return pts, wts, mats
+
+
+def _eval(coef, mats, ders):
+    X = coef
+    for m, B in enumerate(mats):
+        X = mode_product(X, B[ders[m]], m)
+    return X
+
+
+def error_norms(coef, knots, degrees, exact, kappa=1.0):
+    """Relative errors of u_h against ``exact``.
+
+    ``exact`` is a dict of callables on meshgrid arrays (x_1, .., x_d, t):
+    'u', 'ut' (time derivative), 'lap' (spatial Laplacian) and 'grad'
+    (list of spatial first derivatives).  Returns relative errors in the
+    V_0 norm (int int (d_t e)^2 + (Lap e)^2, eq. norm_V0), in L^2 and in the
+    space-time H^1 norm.
+    """
+    d = len(knots) - 1
+    pts, wts, mats = _grid(knots, degrees)
+    G = np.meshgrid(*pts, indexing="ij")
+    W = wts[0]
+    for w in wts[1:]:
+        W = np.multiply.outer(W, w)
+    zero = [0] * (d + 1)
+    uh = _eval(coef, mats, zero)
+    uth = _eval(coef, mats, zero[:d] + [1])
+    laph = sum(_eval(coef, mats, [2 if l == k else 0 for l in range(d)] + [0]) for k in range(d))
+    gradh = [_eval(coef, mats, [1 if l == k else 0 for l in range(d)] + [0]) for k in range(d)]
+    u, ut, lap = exact["u"](*G), exact["ut"](*G), exact["lap"](*G)
+    grad = [g(*G) for g in exact["grad"]]
+
+    def integ(f):
+        return float(np.sum(W * f))
+
+    v0_err = integ((ut - uth) ** 2 + (lap - laph) ** 2)
+    v0_ref = integ(ut ** 2 + lap ** 2)
+    l2_err, l2_ref = integ((u - uh) ** 2), integ(u ** 2)
+    h1_err = l2_err + integ((ut - uth) ** 2) + sum(integ((g - gh) ** 2) for g, gh in zip(grad, gradh))
+    h1_ref = l2_ref + integ(ut ** 2) + sum(integ(g ** 2) for g in grad)
+    return dict(V0=np.sqrt(v0_err / v0_ref), L2=np.sqrt(l2_err / l2_ref), H1=np.sqrt(h1_err / h1_ref))
