@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Benchmark: FD-preconditioned space-time PCG on one MI355X.
+
+One step = one PCG solve of A u = F to ||r||/||b|| <= 1e-8 from u = 0 (all
+hot-path rows: FD preconditioner applications, matrix-free matvecs, vector
+updates and dot products), on the 3-D-space workload: unit cube x (0,1),
+p = 4 (C^3) splines, 48 elements per direction, ndof = 50^3 * 51 = 6,375,000,
+right-hand side i.i.d. uniform[-1,1] (seed 10026), inputs resident in HBM.
+
+The headline value is the mixed-precision solve (FD n-mode products in FP32
+on MFMA inside the FP64 PCG); the FP64-plain solve, per-precision FD
+application rates, the matvec rate, errors, a roofline of the dominant kernel
+(HIP-event durations measured in the timed region) and the oracle timed on the
+host are printed in the same JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FD-prec DOF/s + PCG time-to-1e-8 residual, mixed vs FP64 plain, 1 GPU"
+PEAK = {"hbm_GBs": 8000.0, "fp64_TF": 78.6, "fp32_TF": 157.3, "bf16_TF": 2500.0}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_algorithmic(cls, d, n, N, ns, fd_bytes):
+    """(flops, bytes) per launch of each kernel class (algorithmic counts:
+    dense products without padding, each stream read or written once)."""
+    nt = n[d]
+    if cls == "fd_space":
+        nbar = sum(n[:d]) / d
+        return 2.0 * nbar * N, fd_bytes * N
+    if cls == "fd_time":
+        return 4.0 * nt * N, fd_bytes * N
+    streams = {"mv_inner1": 4, "mv_inner2": 6, "mv_space": 5 if d > 1 else 3, "mv_time": 4}
+    if cls in streams:
+        return None, 8.0 * streams[cls] * N
+    if cls == "mv_last":
+        return None, 8.0 * 3 * ns
+    return None, None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--maxit", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the solver is a single-GPU build (multi-GPU sharding is "
+              "described in DESIGN.md, not implemented); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1809_10026_amd as stls
+    from stls_inputs import CONFIGS, problem_knots, uniform_pm1
+
+    cfg = CONFIGS["cfg3_d3_p4_nel48"]
+    d, nel, p, rtol = cfg["d"], cfg["n_el"], cfg["p"], cfg["rtol"]
+    knots, degs = problem_knots(d, nel, p)
+    torch.cuda.init()
+    t0 = time.perf_counter()
+    S = stls.Solver(knots, degs)
+    setup_s = time.perf_counter() - t0
+    N, shape = S.ndof, S.shape
+    ns = N // shape[d]
+    log(f"setup {setup_s:.3f}s ndof={N} shape={shape}")
+    b = torch.as_tensor(uniform_pm1(N, cfg["seed"])).cuda()
+    x = torch.empty_like(b)
+    z = torch.empty_like(b)
+
+    def timed_solves(mode, steps, warmup, profile):
+        S.set_fd_precision(mode)
+        for _ in range(warmup):
+            S.solve(b, rtol, args.maxit, out=x)
+        S.profile_reset()
+        S.profiling(profile)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        its = []
+        for _ in range(steps):
+            _, it, rel = S.solve(b, rtol, args.maxit, out=x)
+            its.append(it)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        prof = S.profile()
+        S.profiling(False)
+        return dt, its[-1], rel, prof
+
+    def fd_rate(mode, reps=20):
+        S.set_fd_precision(mode)
+        for _ in range(3):
+            S.prec_apply(b, out=z)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            S.prec_apply(b, out=z)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    def true_relres(xs):
+        r = b - S.matvec(xs)
+        return float(torch.linalg.norm(r) / torch.linalg.norm(b))
+
+    modes = {"fp64": stls.STLS_FD_FP64, "fp32": stls.STLS_FD_FP32}
+    res = {}
+    sol = {}
+    for name, mode in modes.items():
+        headline = name == "fp32"
+        dt, it, rel, prof = timed_solves(mode, args.steps, args.warmup, profile=headline)
+        sol[name] = x.clone()
+        res[name] = dict(time_s=dt, iters=it, relres=rel, true_relres=true_relres(x), prof=prof)
+        log(f"{name}: solve {dt*1e3:.3f} ms, {it} its, relres {rel:.2e}, true {res[name]['true_relres']:.2e}")
+    for name, mode in modes.items():
+        res[name]["fd_apply_s"] = fd_rate(mode)
+        log(f"{name}: FD apply {res[name]['fd_apply_s']*1e6:.1f} us")
+    # matvec rate
+    for _ in range(3):
+        S.matvec(b, out=z)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(20):
+        S.matvec(b, out=z)
+    torch.cuda.synchronize()
+    mv_s = (time.perf_counter() - t) / 20
+    err_mixed = float(torch.linalg.norm(sol["fp32"] - sol["fp64"]) / torch.linalg.norm(sol["fp64"]))
+
+    # roofline of the dominant kernel class of the headline (timed) solves
+    prof = res["fp32"]["prof"]
+    classes = []
+    for cls, (launches, ms) in prof.items():
+        if launches == 0:
+            continue
+        flops, byts = kernel_algorithmic(cls, d, shape, N, ns, fd_bytes=8.0)
+        avg_s = ms / launches / 1e3
+        entry = dict(kernel=cls, launches=launches, total_ms=ms, avg_us=avg_s * 1e6)
+        if cls.startswith("fd_"):
+            entry.update(bound="mfma", achieved=flops / avg_s / 1e12, peak=PEAK["fp32_TF"], unit="TFLOP/s")
+        elif byts is not None:
+            entry.update(bound="hbm", achieved=byts / avg_s / 1e9, peak=PEAK["hbm_GBs"], unit="GB/s")
+        if "achieved" in entry:
+            entry["frac"] = entry["achieved"] / entry["peak"]
+        classes.append(entry)
+    classes.sort(key=lambda e: -e["total_ms"])
+    dom = next(e for e in classes if "achieved" in e)
+    roofline = dict(kernel=dom["kernel"], bound=dom["bound"], achieved=round(dom["achieved"], 3),
+                    peak=dom["peak"], unit=dom["unit"], frac=round(dom["frac"], 4), traffic=None,
+                    avg_us=round(dom["avg_us"], 3))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(knots, degs, b.cpu().numpy(), res["fp64"]["iters"], N)
+
+    t_mixed, t_fp64 = res["fp32"]["time_s"], res["fp64"]["time_s"]
+    out = {
+        "metric": METRIC,
+        "value": N / t_mixed,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_mixed * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (PCG) + f32 (FD n-mode products)",
+        "data": "synthetic",
+        "config": {"workload": "d=3 unit cube x (0,1), p=4 C^3 splines, 48 elements/dir, ndof=6375000 "
+                               "(50^3 x 51), RHS U[-1,1] seed 10026, PCG rtol 1e-8 from x0=0",
+                   "ndof": N, "unconstrained_dofs": (nel + p) ** (d + 1), "rtol": rtol},
+        "time_to_tol_s": {"mixed_fp32_fd": t_mixed, "fp64_plain": t_fp64},
+        "speedup_mixed_vs_fp64": t_fp64 / t_mixed,
+        "iters": {"mixed_fp32_fd": res["fp32"]["iters"], "fp64_plain": res["fp64"]["iters"]},
+        "true_relres": {"mixed_fp32_fd": res["fp32"]["true_relres"], "fp64_plain": res["fp64"]["true_relres"]},
+        "err_mixed_vs_fp64_solution": err_mixed,
+        "fd_prec_dof_per_s": {k: N / v["fd_apply_s"] for k, v in res.items()},
+        "matvec_dof_per_s": N / mv_s,
+        "setup_s": setup_s,
+        "roofline": roofline,
+        "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in e.items()} for e in classes],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(knots, degs, b, iters_fp64, N, sample_its=3):
+    """The FP64 oracle's own FD-PCG on the host cores: a bounded sample of
+    ``sample_its`` iterations on the same inputs, scaled to a full solve with
+    the GPU FP64 iteration count (DOF/s)."""
+    import numpy as np
+
+    from oracle import fd, pcg, system
+    threads = None
+    try:
+        import threadpoolctl
+        threads = max((i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()), default=None)
+    except Exception:
+        pass
+    log(f"cpu baseline: oracle PCG, {sample_its} iterations")
+    t0 = time.perf_counter()
+    P = system.Problem(knots, degs)
+    F = fd.FD(P)
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    P.matvec(b)
+    t_mv = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pcg.pcg(lambda v: system.vec(P.matvec(v)), lambda v: system.vec(F.apply(v)), b, 1e-30, maxit=sample_its)
+    dt = time.perf_counter() - t0
+    # pcg() ends with one true-residual matvec, which is not part of an iteration
+    per_it = (dt - t_mv) / sample_its
+    t_solve = per_it * iters_fp64 + setup
+    log(f"cpu baseline: {per_it:.2f} s/iteration")
+    return {"value": N / t_solve, "unit": "DOF/s", "cores": threads or os.cpu_count(), "kind": "oracle",
+            "sample": f"{sample_its} PCG iterations of the numpy FP64 oracle on the same workload "
+                      f"({dt:.1f} s, minus one true-residual matvec of {t_mv:.1f} s), scaled to "
+                      f"{iters_fp64} iterations + setup",
+            "seconds_per_iteration": per_it}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,159 @@
+/*
+ * stls.h -- C ABI of the MI355X (gfx950) space-time least-squares heat solver.
+ *
+ * Method: Montardini, Negri, Sangalli, Tani, "Space-time least-squares
+ * isogeometric method and efficient solver for parabolic problems"
+ * (arXiv:1809.10026).  The heat equation d_t u - kappa Lap u = f on the unit
+ * box (0,1)^d x (0,1) with homogeneous Dirichlet data in space and zero
+ * initial value (§3.1, eq. heat_eq; kappa = 1 in the paper) is discretised
+ * by the least-squares method of §3.2-3.3 with tensor-product B-splines
+ * (§2).  The SPD system A u = F (§4.1, eq. A_kron)
+ *
+ *     A = K_t (x) M_s + kappa^2 M_t (x) J_s + kappa W_t (x) L_s
+ *
+ * is solved by preconditioned conjugate gradients (PCG) with the
+ * preconditioner P = K_t (x) M_s + kappa^2 M_t (x) J~_s (§4.2, eq.
+ * preconditioner) applied by fast diagonalization (§4.3, Algorithm 1).
+ *
+ * Conventions shared by every entry point
+ *  - Vectors are FP64, device-resident (HBM), caller-owned, contiguous, in
+ *    the colexicographic order of §2.2 / eq. kron_vec_multi: first space
+ *    index fastest, ..., d-th space index, time index slowest.  Their
+ *    length is ndof = n_1 * ... * n_d * n_t with n_k = m_k - 2 (Dirichlet
+ *    functions dropped in space) and n_t = m_t - 1 (initial-time function
+ *    dropped), eq. basis_par; m = #knots - degree - 1.
+ *  - Work is enqueued on the stream given at setup and is asynchronous with
+ *    respect to the host, except where a function says it synchronises.
+ *  - No call throws; every call returns a status (stls_status).  A handle
+ *    must not be used from two host threads at once; calls on different
+ *    handles are independent.
+ *  - The handle owns all device memory it allocates (factors, workspace).
+ */
+#ifndef STLS_H
+#define STLS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stls_ctx* stls_handle;
+
+typedef enum stls_status {
+  STLS_OK = 0,
+  STLS_EINVAL = -1,     /* invalid argument (knots, degrees, sizes, pointers, mode) */
+  STLS_ENOMEM = -2,     /* device or host allocation failed */
+  STLS_EHIP = -3,       /* a HIP runtime call failed; see stls_last_error */
+  STLS_ENOCONV = -4,    /* PCG hit maxit before reaching rtol */
+  STLS_ENAN = -5,       /* NaN or Inf met in the right-hand side or the iteration */
+  STLS_EBREAKDOWN = -6  /* PCG breakdown: p^T A p <= 0 or r^T z <= 0 */
+} stls_status;
+
+typedef enum stls_fd_precision {
+  STLS_FD_FP64 = 0,    /* n-mode products in FP64 (MFMA f64) */
+  STLS_FD_FP32 = 1,    /* n-mode products and intermediates in FP32 (MFMA f32) */
+  STLS_FD_BF16X3 = 2   /* FP32 operands split into bf16 hi+lo, three bf16 MFMA
+                          products (hi*hi + hi*lo + lo*hi), FP32 accumulation */
+} stls_fd_precision;
+
+/*
+ * stls_setup -- build a solver for one problem (§2.1-2.2, §4.1-4.3 step 1).
+ *  d        number of space dimensions, 1..3.
+ *  nknots   d + 1 knot-vector lengths (space directions 1..d, then time).
+ *  knots    d + 1 host arrays, copied: open knot vectors on [0,1] (§2.1):
+ *           non-decreasing, first p+1 entries 0 and last p+1 entries 1.
+ *  degree   d + 1 degrees.  Space: p >= 2 and every interior knot of
+ *           multiplicity <= p - 1 (C^1 splines, Assumption 2); time:
+ *           p >= 1 and multiplicity <= p (C^0).
+ *  kappa    diffusivity > 0 (1 = the paper's model problem).
+ *  stream   hipStream_t to enqueue on (NULL = default stream).
+ *  out      receives the handle.
+ * Host work: Gauss quadrature of the banded univariate matrices, generalized
+ * eigendecompositions J_k U = M_k U Lambda and K_t U = M_t U Lambda with
+ * U^T M U = I (eq. eig_dec), upload.  Synchronises the stream.
+ * Errors: STLS_EINVAL for invalid input (nothing allocated), STLS_ENOMEM,
+ * STLS_EHIP.
+ */
+int stls_setup(int d, const int* nknots, const double* const* knots, const int* degree,
+               double kappa, void* stream, stls_handle* out);
+
+/* Release every device and host resource of the handle (NULL is a no-op). */
+int stls_destroy(stls_handle h);
+
+/* Sizes: n[0..d] receives n_1..n_d, n_t; *ndof receives their product. */
+int stls_get_shape(stls_handle h, int* n, int64_t* ndof);
+
+/*
+ * Copy setup results to host memory (test and inspection use).
+ *  dir   0..d-1 space direction, d = time.
+ *  what  0 = mass M, 1 = stiffness K, 2 = bilaplacian J (space only): banded
+ *        restricted matrix, n x (2p+1) row-major, entry (i,j) at
+ *        i*(2p+1) + (j - i + p), zero outside 0 <= j < n;
+ *        3 = eigenvectors U, n x n column-major (U^T M U = I);
+ *        4 = eigenvalues, n values;
+ *        5 = final-time weight b_last(1)^2 (time only), 1 value.
+ *  out   host buffer of the documented size; *count receives #doubles.
+ * Pass out = NULL to query *count only.
+ */
+int stls_get_factor(stls_handle h, int dir, int what, double* out, int64_t* count);
+
+/* Change kappa (> 0): rescales the summed eigenvalues; U is independent of kappa. */
+int stls_set_kappa(stls_handle h, double kappa);
+
+/* Select the arithmetic of the FD n-mode products (stls_fd_precision).
+ * The eigenvalue division, PCG vectors and dot products stay FP64. */
+int stls_set_fd_precision(stls_handle h, int mode);
+
+/*
+ * s = P^{-1} r by Algorithm 1 steps 2-4 (§4.3): n-mode products with U^T
+ * over every direction, division by lambda_t[i_t] + kappa^2 sum_k
+ * lambda_k[i_k], n-mode products with U.  r, s: device, ndof doubles, may
+ * not alias.  Asynchronous.
+ */
+int stls_prec_apply(stls_handle h, const double* r, double* s);
+
+/*
+ * y = A x, matrix-free from the banded univariate factors (§4.5; eq. A_kron
+ * with kappa).  x, y: device, ndof doubles, may not alias.  Asynchronous.
+ */
+int stls_matvec(stls_handle h, const double* x, double* y);
+
+/*
+ * PCG for A x = b (§4.2; tolerance and zero start as in §5).
+ *  b      device, ndof doubles.
+ *  x      device, ndof doubles: output (the iteration starts from x = 0;
+ *         incoming contents are ignored).
+ *  rtol   stop when the recurrence residual satisfies ||r||_2/||b||_2 <= rtol.
+ *  maxit  iteration cap (>= 1).
+ *  iters, relres  host outputs (may be NULL): iterations done, final
+ *         recurrence relative residual.
+ * Synchronises the stream.  Returns STLS_OK on convergence, STLS_ENOCONV at
+ * maxit, STLS_ENAN for a non-finite b or iterate, STLS_EBREAKDOWN if a
+ * curvature or r^T z is not positive.  b = 0 returns x = 0, iters = 0.
+ */
+int stls_pcg_solve(stls_handle h, const double* b, double* x, double rtol, int maxit,
+                   int* iters, double* relres);
+
+/* Residual history of the last stls_pcg_solve: out[k] = ||r_k||/||b||,
+ * k = 0..iters (host buffer of at least max entries); *count = iters + 1. */
+int stls_pcg_history(stls_handle h, double* out, int max, int* count);
+
+/* Per-kernel timing with HIP events on the handle's stream (0 = off). */
+int stls_set_profiling(stls_handle h, int on);
+/* Kernel class names and accumulated (launches, milliseconds) since the last
+ * reset.  idx in [0, stls_profile_count()); name receives a static string. */
+int stls_profile_count(void);
+int stls_profile_get(stls_handle h, int idx, const char** name, int64_t* launches, double* ms);
+int stls_profile_reset(stls_handle h);
+
+/* Human-readable status text (static storage). */
+const char* stls_status_string(int status);
+/* Text of the last error recorded on this thread (static per-thread storage). */
+const char* stls_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STLS_H */

@@ -1,0 +1,263 @@
+"""MI355X-native space-time least-squares heat solver (Python binding).
+
+Thin ctypes binding over ``libstls.so`` (C ABI in ``include/stls.h``).  It only
+marshals arguments: every step of the solve (FD preconditioner, matvec, PCG)
+runs in the library's HIP kernels.  PyTorch supplies device memory and the
+current stream.  If the library has not been built, importing this package
+raises ImportError: there is no CPU fallback.
+
+Method: Montardini, Negri, Sangalli, Tani, arXiv:1809.10026 (space-time
+least-squares isogeometric discretisation of the heat equation, §3; Kronecker
+system, §4.1; FD-preconditioned PCG, §4.2-4.3).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "LIB_PATH", "STLS_OK", "STLS_FD_FP64", "STLS_FD_FP32", "STLS_FD_BF16X3", "StlsError",
+    "stls_setup", "stls_destroy", "stls_get_shape", "stls_get_factor", "stls_set_kappa",
+    "stls_set_fd_precision", "stls_prec_apply", "stls_matvec", "stls_pcg_solve",
+    "stls_pcg_history", "stls_set_profiling", "stls_profile", "stls_profile_reset",
+    "Solver",
+]
+
+# torch first: its HIP runtime (same soname as ROCm's) then also serves the
+# library, so the process holds a single runtime and shares device pointers
+# and streams with torch.
+import torch  # noqa: E402,F401
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstls.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_1809_10026_amd.build` "
+        "(there is no CPU fallback)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+STLS_OK, STLS_EINVAL, STLS_ENOMEM, STLS_EHIP, STLS_ENOCONV, STLS_ENAN, STLS_EBREAKDOWN = 0, -1, -2, -3, -4, -5, -6
+STLS_FD_FP64, STLS_FD_FP32, STLS_FD_BF16X3 = 0, 1, 2
+
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_dbl_p = ctypes.c_void_p
+_sig = {
+    "stls_setup": (ctypes.c_int, [ctypes.c_int, _c_int_p, ctypes.POINTER(ctypes.c_void_p), _c_int_p,
+                                  ctypes.c_double, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "stls_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "stls_get_shape": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, ctypes.POINTER(ctypes.c_int64)]),
+    "stls_get_factor": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_int64)]),
+    "stls_set_kappa": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
+    "stls_set_fd_precision": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "stls_prec_apply": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
+    "stls_matvec": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
+    "stls_pcg_solve": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, ctypes.c_double, ctypes.c_int,
+                                      _c_int_p, ctypes.POINTER(ctypes.c_double)]),
+    "stls_pcg_history": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, _c_int_p]),
+    "stls_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "stls_profile_count": (ctypes.c_int, []),
+    "stls_profile_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
+    "stls_profile_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "stls_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "stls_last_error": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class StlsError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.stls_status_string(status).decode()
+        detail = _lib.stls_last_error().decode()
+        super().__init__(f"{where}: {msg} ({status}){': ' + detail if detail else ''}")
+
+
+def _check(status, where, ok=(STLS_OK,)):
+    if status not in ok:
+        raise StlsError(status, where)
+    return status
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, n, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# C ABI mirrors (same names); handles are opaque ctypes.c_void_p values.
+
+def stls_setup(knots, degrees, kappa=1.0, stream=None):
+    """Handle for one problem; knots: d+1 host arrays (time last)."""
+    d = len(knots) - 1
+    arrs = [np.ascontiguousarray(k, dtype=np.float64) for k in knots]
+    nk = (ctypes.c_int * (d + 1))(*[len(a) for a in arrs])
+    ptrs = (ctypes.c_void_p * (d + 1))(*[a.ctypes.data for a in arrs])
+    degs = (ctypes.c_int * (d + 1))(*[int(p) for p in degrees])
+    h = ctypes.c_void_p()
+    _check(_lib.stls_setup(d, nk, ptrs, degs, float(kappa), _stream_ptr(stream), ctypes.byref(h)), "stls_setup")
+    return h
+
+
+def stls_destroy(h):
+    _check(_lib.stls_destroy(h), "stls_destroy")
+
+
+def stls_get_shape(h, d):
+    n = (ctypes.c_int * (d + 1))()
+    nd = ctypes.c_int64()
+    _check(_lib.stls_get_shape(h, n, ctypes.byref(nd)), "stls_get_shape")
+    return tuple(n), int(nd.value)
+
+
+def stls_get_factor(h, direction, what):
+    cnt = ctypes.c_int64()
+    _check(_lib.stls_get_factor(h, direction, what, None, ctypes.byref(cnt)), "stls_get_factor")
+    out = np.zeros(cnt.value)
+    _check(_lib.stls_get_factor(h, direction, what, out.ctypes.data, ctypes.byref(cnt)), "stls_get_factor")
+    return out
+
+
+def stls_set_kappa(h, kappa):
+    _check(_lib.stls_set_kappa(h, float(kappa)), "stls_set_kappa")
+
+
+def stls_set_fd_precision(h, mode):
+    _check(_lib.stls_set_fd_precision(h, int(mode)), "stls_set_fd_precision")
+
+
+def stls_prec_apply(h, ndof, r, s):
+    _check(_lib.stls_prec_apply(h, _dev_ptr(r, ndof, "r"), _dev_ptr(s, ndof, "s")), "stls_prec_apply")
+
+
+def stls_matvec(h, ndof, x, y):
+    _check(_lib.stls_matvec(h, _dev_ptr(x, ndof, "x"), _dev_ptr(y, ndof, "y")), "stls_matvec")
+
+
+def stls_pcg_solve(h, ndof, b, x, rtol, maxit, raise_on_noconv=True):
+    it = ctypes.c_int()
+    rel = ctypes.c_double()
+    ok = (STLS_OK,) if raise_on_noconv else (STLS_OK, STLS_ENOCONV)
+    st = _check(_lib.stls_pcg_solve(h, _dev_ptr(b, ndof, "b"), _dev_ptr(x, ndof, "x"), float(rtol), int(maxit),
+                                    ctypes.byref(it), ctypes.byref(rel)), "stls_pcg_solve", ok)
+    return int(it.value), float(rel.value), st
+
+
+def stls_pcg_history(h):
+    cnt = ctypes.c_int()
+    _check(_lib.stls_pcg_history(h, None, 0, ctypes.byref(cnt)), "stls_pcg_history")
+    out = np.zeros(cnt.value)
+    _check(_lib.stls_pcg_history(h, out.ctypes.data, cnt.value, ctypes.byref(cnt)), "stls_pcg_history")
+    return out
+
+
+def stls_set_profiling(h, on):
+    _check(_lib.stls_set_profiling(h, 1 if on else 0), "stls_set_profiling")
+
+
+def stls_profile(h):
+    """{kernel class: (launches, total ms)} accumulated since the last reset."""
+    res = {}
+    for i in range(_lib.stls_profile_count()):
+        name = ctypes.c_char_p()
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(_lib.stls_profile_get(h, i, ctypes.byref(name), ctypes.byref(n), ctypes.byref(ms)), "stls_profile_get")
+        res[name.value.decode()] = (int(n.value), float(ms.value))
+    return res
+
+
+def stls_profile_reset(h):
+    _check(_lib.stls_profile_reset(h), "stls_profile_reset")
+
+
+# ---------------------------------------------------------------------------
+class Solver:
+    """One space-time heat problem on the unit box; owns a library handle.
+
+    knots/degrees: d+1 entries (space directions, then time).  Vectors are
+    float64 CUDA tensors of ``ndof`` entries in colexicographic order.
+    """
+
+    def __init__(self, knots, degrees, kappa=1.0, stream=None):
+        self.d = len(knots) - 1
+        self._h = stls_setup(knots, degrees, kappa, stream)
+        self.shape, self.ndof = stls_get_shape(self._h, self.d)
+        self.kappa = float(kappa)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            stls_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _empty(self):
+        import torch
+        return torch.empty(self.ndof, dtype=torch.float64, device="cuda")
+
+    def set_kappa(self, kappa):
+        stls_set_kappa(self._h, kappa)
+        self.kappa = float(kappa)
+
+    def set_fd_precision(self, mode):
+        stls_set_fd_precision(self._h, mode)
+
+    def factor(self, direction, what):
+        return stls_get_factor(self._h, direction, what)
+
+    def prec_apply(self, r, out=None):
+        s = self._empty() if out is None else out
+        stls_prec_apply(self._h, self.ndof, r, s)
+        return s
+
+    def matvec(self, x, out=None):
+        y = self._empty() if out is None else out
+        stls_matvec(self._h, self.ndof, x, y)
+        return y
+
+    def solve(self, b, rtol=1e-8, maxit=500, out=None, raise_on_noconv=True):
+        x = self._empty() if out is None else out
+        it, rel, st = stls_pcg_solve(self._h, self.ndof, b, x, rtol, maxit, raise_on_noconv)
+        return x, it, rel
+
+    def history(self):
+        return stls_pcg_history(self._h)
+
+    def profiling(self, on=True):
+        stls_set_profiling(self._h, on)
+
+    def profile(self):
+        return stls_profile(self._h)
+
+    def profile_reset(self):
+        stls_profile_reset(self._h)

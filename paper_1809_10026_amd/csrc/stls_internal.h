@@ -1,0 +1,138 @@
+// Internal declarations of the stls library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/stls.h"
+
+namespace stls {
+
+constexpr int kMaxDim = 3;          // space dimensions supported
+constexpr int kMaxDirN = 256;       // largest restricted size per direction
+constexpr int kPartialsCap = 1 << 16;
+
+// Host-side description of one parametric direction (space k or time).
+struct Dir {
+  int p = 0;        // degree
+  int m = 0;        // number of B-splines of the knot vector
+  int n = 0;        // restricted size (space: m - 2, time: m - 1)
+  bool is_time = false;
+  std::vector<double> knots;
+  // banded restricted matrices, n x (2p+1), entry (i,j) at i*(2p+1)+(j-i+p)
+  std::vector<double> M, K, J;
+  std::vector<double> U;    // n x n column-major, U^T M U = I
+  std::vector<double> lam;  // generalized eigenvalues
+  double wend = 0.0;        // b_{m}(1)^2 (time): the single entry of W_t
+};
+
+// Device copies of one direction.
+struct DevDir {
+  int p = 0, n = 0, npad = 0;  // npad: n rounded up to 16
+  double* M = nullptr;         // banded, n x (2p+1)
+  double* K = nullptr;
+  double* J = nullptr;
+  double* Afwd64 = nullptr;    // FD operand for the U^T product: [j*npad + i] = U(j,i)
+  double* Abwd64 = nullptr;    // FD operand for the U product:   [j*npad + i] = U(i,j)
+  float* Afwd32 = nullptr;
+  float* Abwd32 = nullptr;
+  uint16_t* Hfwd = nullptr;    // bf16 hi/lo of W, row-major [i*kpad + k], kpad = n rounded to 32
+  uint16_t* Lfwd = nullptr;
+  uint16_t* Hbwd = nullptr;
+  uint16_t* Lbwd = nullptr;
+  int kpad = 0;
+  double* lam = nullptr;
+};
+
+// Scalars of the PCG recurrence, resident in device memory.
+struct PcgScalars {
+  double rho;      // r^T z of the current iterate
+  double alpha, beta;
+  double bnorm2;   // ||b||^2
+  double relres;   // ||r||/||b||
+  double rtol;
+  int done;        // set once relres <= rtol (later kernels become no-ops)
+  int flag;        // 0 ok, 1 breakdown, 2 non-finite
+  int iters;
+  int pad;
+};
+
+enum ProfId {
+  PROF_FD_SPACE = 0,  // dense n-mode product over one space direction
+  PROF_FD_TIME,       // fused time-mode forward product / division / backward product
+  PROF_MV_INNER1,     // matvec: banded products along space direction 1
+  PROF_MV_INNER2,     // matvec: banded products along space direction 2 (d = 3)
+  PROF_MV_SPACE,      // matvec: banded products along the last space direction
+  PROF_MV_LAST,       // matvec: final-time slice term (W_t)
+  PROF_MV_TIME,       // matvec: banded products along time (+ fused dot)
+  PROF_VEC,           // PCG vector kernels
+  PROF_REDUCE,        // PCG scalar finalisation kernels
+  PROF_COUNT
+};
+
+struct stls_ctx_impl;
+
+}  // namespace stls
+
+struct stls_ctx {
+  int d = 0;
+  double kappa = 1.0;
+  hipStream_t stream = nullptr;
+  int fd_mode = STLS_FD_FP64;
+  stls::Dir dir[stls::kMaxDim + 1];
+  stls::DevDir dd[stls::kMaxDim + 1];
+  int64_t ndof = 0, ns = 0;  // ns = spatial dofs
+  double* lam_s = nullptr;   // kappa^2 * sum_k lambda_k[i_k], length ns
+  double* lam_s_raw = nullptr;  // sum_k lambda_k[i_k] (kappa-free), length ns
+  // workspace
+  double* work[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* fdbuf[2] = {nullptr, nullptr};   // FD ping-pong (also used as float)
+  double* r = nullptr;
+  double* z = nullptr;
+  double* pvec = nullptr;
+  double* q = nullptr;
+  double* partials = nullptr;
+  stls::PcgScalars* scal = nullptr;
+  stls::PcgScalars* scal_host = nullptr;  // pinned
+  std::vector<double> history;
+  int last_iters = 0;
+  // profiling
+  bool prof = false;
+  struct PendingEv { hipEvent_t a, b; int id; };
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<PendingEv> ev_pending;
+  hipEvent_t ev_open = nullptr;
+  int64_t prof_launch[stls::PROF_COUNT] = {0};
+  double prof_ms[stls::PROF_COUNT] = {0};
+};
+
+namespace stls {
+
+// error reporting
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+// host setup (stls_host.cpp)
+int validate_and_build_dir(const double* knots, int nknots, int p, bool is_time, Dir& out,
+                           std::string& err);
+void sym_generalized_eig(int n, const std::vector<double>& Kdense, const std::vector<double>& Mdense,
+                         std::vector<double>& U, std::vector<double>& lam);
+
+// kernel launchers (stls_kernels.hip)
+int launch_prec_apply(stls_ctx* h, const double* r, double* s, const double* dot_with,
+                      double* partials_out, int* nparts);
+int launch_matvec(stls_ctx* h, const double* x, double* y, const double* dot_with, double* partials_out,
+                  int* nparts);
+int pcg_run(stls_ctx* h, const double* b, double* x, double rtol, int maxit, int* iters,
+            double* relres);
+int upload_fd_operands(stls_ctx* h, int k);
+
+// profiling helpers
+void prof_begin(stls_ctx* h);
+void prof_end(stls_ctx* h, int id);
+void prof_flush(stls_ctx* h);
+
+}  // namespace stls
