@@ -529,7 +529,7 @@ int stls_setup(int d, const int* nknots, const double* const* knots, const int* 
       st = e == hipErrorOutOfMemory ? STLS_ENOMEM : STLS_EHIP;
     }
   };
-  const int nwork = d == 1 ? 2 : (d == 2 ? 5 : 6);
+  const int nwork = d == 1 ? 0 : 3;
   for (int i = 0; i < nwork; ++i) alloc(&h->work[i], nb);
   alloc(&h->fdbuf[0], nb);
   alloc(&h->fdbuf[1], nb);
@@ -613,8 +613,8 @@ int stls_pcg_history(stls_handle h, double* out, int max, int* count) {
   return STLS_OK;
 }
 
-static const char* kProfNames[PROF_COUNT] = {"fd_space", "fd_time", "mv_inner1", "mv_inner2", "mv_space",
-                                             "mv_last", "mv_time", "vec", "reduce"};
+static const char* kProfNames[PROF_COUNT] = {"fd_space", "fd_time", "mv_inner1", "mv_inner2", "mv_outer",
+                                             "vec", "reduce"};
 
 int stls_set_profiling(stls_handle h, int on) {
   if (!h) { set_error("NULL handle"); return STLS_EINVAL; }

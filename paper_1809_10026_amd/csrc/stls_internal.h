@@ -63,11 +63,9 @@ struct PcgScalars {
 enum ProfId {
   PROF_FD_SPACE = 0,  // dense n-mode product over one space direction
   PROF_FD_TIME,       // fused time-mode forward product / division / backward product
-  PROF_MV_INNER1,     // matvec: banded products along space direction 1
-  PROF_MV_INNER2,     // matvec: banded products along space direction 2 (d = 3)
-  PROF_MV_SPACE,      // matvec: banded products along the last space direction
-  PROF_MV_LAST,       // matvec: final-time slice term (W_t)
-  PROF_MV_TIME,       // matvec: banded products along time (+ fused dot)
+  PROF_MV_INNER1,     // matvec inner stage, d = 2 (space direction 1)
+  PROF_MV_INNER2,     // matvec inner stage, d = 3 (space directions 1 and 2)
+  PROF_MV_OUTER,      // matvec outer stage (last space direction and time)
   PROF_VEC,           // PCG vector kernels
   PROF_REDUCE,        // PCG scalar finalisation kernels
   PROF_COUNT

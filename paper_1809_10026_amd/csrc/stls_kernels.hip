@@ -30,7 +30,7 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 constexpr int kCols = 64;          // FD panel width (columns per workgroup)
-constexpr int kLdx = kCols + 1;    // LDS row stride of a panel (elements)
+constexpr int kLdx = kCols + 16;   // LDS row stride of a panel: rows fill distinct banks
 constexpr int kMaxBlocksEW = 8192; // grid cap of grid-stride elementwise kernels
 
 // ---------------------------------------------------------------------------
@@ -69,131 +69,260 @@ template <> struct Mfma<float> {
 };
 
 // ---------------------------------------------------------------------------
-// FD mode product on one panel of kCols columns:
-//   Y(i, c) = sum_j W(i, j) X(j, c),   W given as A[j*npad + i] (zero padded)
-// TC: compute type (double -> MFMA f64, float -> MFMA f32); TI/TO: storage
-// types of input/output.  With fused_time the panel is the time mode (L =
-// number of spatial dofs, one column per spatial index) and the kernel applies
-// Y -> (Y / (lambda_t[i] + lambda_s[c])) -> W2 Y before storing (Algorithm 1
-// steps 2 (time part), 3 and 4 (time part)); the division is FP64.
-// With dotv != nullptr each block also writes sum(Y .* dotv) to partials.
-template <typename TC, typename TI, typename TO, int NM>
+// Hand the logical tile index of a block so that consecutive logical tiles
+// run on the same XCD (blocks are dealt round-robin to the 8 XCDs, each with
+// its own L2): neighbouring tiles then share halo and operand lines in L2.
+__device__ inline int xcd_tile(int bid, int nblocks) {
+  constexpr int kXcd = 8;
+  const int full = nblocks - nblocks % kXcd;
+  if (bid >= full) return bid;
+  return (bid % kXcd) * (full / kXcd) + bid / kXcd;
+}
+
+// ---------------------------------------------------------------------------
+// FD mode product, one panel of kCols columns at a time:
+//   Y(i, c) = sum_j W(i, j) X(j, c),   W read as Aop[j*npad + i] (zero padded)
+// The operand W is staged in LDS once per workgroup; the workgroup then loops
+// over panels (grid-stride).  A panel is staged through LDS with coalesced
+// loads; results go straight from the MFMA registers to HBM in 16-wide
+// contiguous runs.  TRANS selects the orientation: for the contiguous mode
+// (L == 1) the MFMA rows are panel columns (output rows of 16 contiguous i),
+// otherwise MFMA rows are i and the 16 lanes of a row are contiguous columns.
+// TC: compute type (double -> MFMA f64, float -> MFMA f32); TI/TO storage
+// types.  fused_time: time mode, Y -> (Y / (lambda_t[i] + lambda_s[c])) -> W2 Y
+// (Algorithm 1, time part of step 2, step 3, time part of step 4), division
+// in FP64.  dotv: each block adds sum(Y .* dotv) of its panels to partials.
+template <typename TC, typename TI, typename TO, int NM, bool TRANS, bool WLDS, bool FUSED, bool DOT>
 __global__ __launch_bounds__(kThreads) void fd_mode_kernel(
-    const TI* __restrict__ X, TO* __restrict__ Y, int L, int n, int ncols, const TC* __restrict__ A,
-    int npad, int fused_time, const TC* __restrict__ A2, const double* __restrict__ lam_t,
-    const double* __restrict__ lam_s, const double* __restrict__ dotv, double* __restrict__ partials) {
+    const TI* __restrict__ X, TO* __restrict__ Y, int L, int n, int ncols, const TC* __restrict__ Aop,
+    const TC* __restrict__ Aop2, int w2lds, const double* __restrict__ lam_t, const double* __restrict__ lam_s,
+    const double* __restrict__ dotv, double* __restrict__ partials) {
+  constexpr int NPAD = NM * 16;
+  constexpr int PER = NPAD * kCols / kThreads;  // panel entries per thread
+  constexpr bool PREF = NM <= 4;                // register prefetch of the next panel
+  constexpr int LDW = NPAD + 16;                // rows of 16-lane fragments land on distinct banks
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  TC* Xs = reinterpret_cast<TC*>(smem_raw);                        // npad x kLdx
-  int* colbase = reinterpret_cast<int*>(smem_raw + sizeof(TC) * npad * kLdx);  // kCols
-  double* red = reinterpret_cast<double*>(colbase + kCols);        // 4 (8-byte aligned: kCols ints)
+  TC* Ws = reinterpret_cast<TC*>(smem_raw);            // NPAD x LDW (if WLDS)
+  TC* Ws2 = Ws + (WLDS ? NPAD * LDW : 0);              // second operand (if w2lds)
+  TC* Xs = Ws2 + (w2lds ? NPAD * LDW : 0);             // NPAD x kLdx: panel
+  double* red = reinterpret_cast<double*>(Xs + NPAD * kLdx);
   typedef typename Mfma<TC>::acc_t acc_t;
+  const TC* __restrict__ Wsrc = WLDS ? Ws : Aop;
+  const int ldw1 = WLDS ? LDW : NPAD;
+  const TC* __restrict__ W2src = w2lds ? Ws2 : Aop2;
+  const int ldw2 = w2lds ? LDW : NPAD;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int c0 = blockIdx.x * kCols;
-  if (tid < kCols) {
-    const int cc = c0 + tid;
-    colbase[tid] = (cc < ncols) ? (cc % L) + (cc / L) * L * n : -1;
-  }
-  __syncthreads();
-  const int total = kCols * npad;
-  for (int e = tid; e < total; e += kThreads) {
-    int j, c;
-    if (L == 1) { c = e / npad; j = e - c * npad; }   // columns are contiguous in memory
-    else { j = e / kCols; c = e - j * kCols; }        // rows of kCols contiguous entries
-    const int b = colbase[c];
-    TC v = TC(0);
-    if (j < n && b >= 0) v = (TC)X[(size_t)b + (size_t)j * L];
-    Xs[j * kLdx + c] = v;
-  }
-  __syncthreads();
-
-  acc_t acc[NM];
+  const int npanels = (ncols + kCols - 1) / kCols;
   const int ccol = wave * 16 + (lane & 15);
   const int krow = lane >> 4;
-  auto gemm = [&](const TC* __restrict__ W) {
-#pragma unroll
-    for (int mt = 0; mt < NM; ++mt) acc[mt] = acc_t{0, 0, 0, 0};
-    for (int k0 = 0; k0 < n; k0 += 4) {
-      const TC b = Xs[(k0 + krow) * kLdx + ccol];
-      const TC* __restrict__ Ap = W + (size_t)(k0 + krow) * npad + (lane & 15);
-#pragma unroll
-      for (int mt = 0; mt < NM; ++mt) acc[mt] = Mfma<TC>::step(Ap[mt * 16], b, acc[mt]);
+  double dsum = 0.0;
+
+  if (WLDS)
+    for (int e = tid; e < NPAD * NPAD; e += kThreads) {
+      const int j = e / NPAD, i = e - j * NPAD;
+      Ws[j * LDW + i] = Aop[e];
     }
-  };
-  gemm(A);
-  if (fused_time) {
-    __syncthreads();  // every wave is done reading the panel
-    const int cc = c0 + ccol;
-    const double ls = (cc < ncols) ? lam_s[cc] : 1.0;
+  if (FUSED && w2lds)
+    for (int e = tid; e < NPAD * NPAD; e += kThreads) {
+      const int j = e / NPAD, i = e - j * NPAD;
+      Ws2[j * LDW + i] = Aop2[e];
+    }
+  // eigenvalues of this thread's output rows (rows are fixed per lane)
+  double lt[FUSED ? NM * 4 : 1];
+  if constexpr (FUSED) {
 #pragma unroll
-    for (int mt = 0; mt < NM; ++mt)
+    for (int t = 0; t < NM; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = mt * 16 + Mfma<TC>::row(lane, r);
-        double v = 0.0;
-        if (i < n && cc < ncols) v = (double)acc[mt][r] / (lam_t[i] + ls);
-        Xs[i * kLdx + ccol] = (TC)v;
+        const int i = t * 16 + Mfma<TC>::row(lane, r);
+        lt[t * 4 + r] = lam_t[min(i, n - 1)];
       }
-    __syncthreads();
-    gemm(A2);
   }
-  __syncthreads();
+
+  // Column c of the (L, n, R) view starts at base(c) = c % L + (c / L) * L * n.
+  auto column_base = [&](int cc) -> int {
+    if constexpr (TRANS) return cc * n;
+    return (cc % L) + (cc / L) * L * n;
+  };
+  // Panel entry s of this thread: strided layout (64 contiguous columns per
+  // row): c = tid % 64, j = tid / 64 + 4 s; contiguous columns (TRANS):
+  // e = tid + 256 s, c = e / NPAD, j = e % NPAD.  Loads are unconditional
+  // (clamped address) so that no branch separates them from their use.
+  TI pre[PREF ? PER : 1];
+  auto fetch_panel = [&](int c0p, TI* dst) {
+    if constexpr (TRANS) {
 #pragma unroll
-  for (int mt = 0; mt < NM; ++mt)
+      for (int s = 0; s < PER; ++s) {
+        const int e = tid + kThreads * s;
+        const int c = e / NPAD, j = e - c * NPAD;
+        const int cc = c0p + c;
+        const bool ok = cc < ncols && j < n;
+        const TI v = X[ok ? (size_t)cc * n + j : 0];
+        dst[s] = ok ? v : TI(0);
+      }
+    } else {
+      const int cc = c0p + (tid & (kCols - 1));
+      const bool okc = cc < ncols;
+      const size_t b = okc ? (size_t)column_base(cc) : 0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) Xs[(mt * 16 + Mfma<TC>::row(lane, r)) * kLdx + ccol] = acc[mt][r];
-  __syncthreads();
-  double dsum = 0.0;
-  for (int e = tid; e < total; e += kThreads) {
-    int j, c;
-    if (L == 1) { c = e / npad; j = e - c * npad; }
-    else { j = e / kCols; c = e - j * kCols; }
-    const int b = colbase[c];
-    if (j < n && b >= 0) {
-      const size_t off = (size_t)b + (size_t)j * L;
-      const TO v = (TO)Xs[j * kLdx + c];
-      Y[off] = v;
-      if (dotv) dsum += (double)v * dotv[off];
+      for (int s = 0; s < PER; ++s) {
+        const int j = (tid >> 6) + (kThreads / kCols) * s;
+        const bool ok = okc && j < n;
+        const TI v = X[ok ? b + (size_t)j * L : 0];
+        dst[s] = ok ? v : TI(0);
+      }
     }
+  };
+  auto park_entry = [&](int s, TC v) {
+    int j, c;
+    if constexpr (TRANS) { const int e = tid + kThreads * s; c = e / NPAD; j = e - c * NPAD; }
+    else { c = tid & (kCols - 1); j = (tid >> 6) + (kThreads / kCols) * s; }
+    Xs[j * kLdx + c] = v;
+  };
+
+  acc_t acc[NM];
+  // W(i, j) sits at W[j*ldw + i] (LDS copy or the global operand).
+  auto gemm = [&](const TC* __restrict__ W, int ldw) {
+#pragma unroll
+    for (int t = 0; t < NM; ++t) acc[t] = acc_t{0, 0, 0, 0};
+    for (int k0 = 0; k0 < n; k0 += 4) {
+      const TC xv = Xs[(k0 + krow) * kLdx + ccol];
+#pragma unroll
+      for (int t = 0; t < NM; ++t) {
+        const TC wv = W[(k0 + krow) * ldw + t * 16 + (lane & 15)];
+        if constexpr (TRANS) acc[t] = Mfma<TC>::step(xv, wv, acc[t]);
+        else acc[t] = Mfma<TC>::step(wv, xv, acc[t]);
+      }
+    }
+  };
+  // output position of accumulator (t, r): offset base + i * L
+  auto out_pos = [&](int c0p, int t, int r, int& i, int& cc) {
+    if constexpr (TRANS) { cc = c0p + wave * 16 + Mfma<TC>::row(lane, r); i = t * 16 + (lane & 15); }
+    else { cc = c0p + ccol; i = t * 16 + Mfma<TC>::row(lane, r); }
+  };
+
+  if constexpr (PREF) {
+    if (blockIdx.x < npanels) fetch_panel(blockIdx.x * kCols, pre);
   }
-  if (dotv) {
+  for (int pn = blockIdx.x; pn < npanels; pn += gridDim.x) {
+    const int c0 = pn * kCols;
+    __syncthreads();  // W staged; previous panel's readers of Xs are done
+    if constexpr (PREF) {
+#pragma unroll
+      for (int s = 0; s < PER; ++s) park_entry(s, (TC)pre[s]);
+    } else {
+      TI tmp[PER];
+      fetch_panel(c0, tmp);
+#pragma unroll
+      for (int s = 0; s < PER; ++s) park_entry(s, (TC)tmp[s]);
+    }
+    // per-panel operands needed after the GEMM, loaded before the prefetch
+    // of the next panel is issued (loads complete in order)
+    double ls = 1.0;
+    if constexpr (FUSED) ls = lam_s[min(c0 + ccol, ncols - 1)];
+    double dv[DOT ? NM * 4 : 1];
+    if constexpr (DOT) {
+#pragma unroll
+      for (int t = 0; t < NM; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int i, cc;
+          out_pos(c0, t, r, i, cc);
+          const bool ok = cc < ncols && i < n;
+          const double v = dotv[ok ? (size_t)column_base(cc) + (size_t)i * L : 0];
+          dv[t * 4 + r] = ok ? v : 0.0;
+        }
+    }
+    __syncthreads();
+    if constexpr (PREF) {
+      const int nx = pn + gridDim.x;
+      if (nx < npanels) fetch_panel(nx * kCols, pre);
+    }
+    gemm(Wsrc, ldw1);
+    if constexpr (FUSED) {
+      // Q = (U_t^T X) / Lambda, then U_t Q with the backward operand.
+      __syncthreads();  // all waves are done reading Xs
+#pragma unroll
+      for (int t = 0; t < NM; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = t * 16 + Mfma<TC>::row(lane, r);
+          const double v = (double)acc[t][r] / (lt[t * 4 + r] + ls);
+          Xs[i * kLdx + ccol] = (i < n) ? (TC)v : TC(0);
+        }
+      __syncthreads();
+      gemm(W2src, ldw2);
+    }
+    // direct stores from the accumulators
+#pragma unroll
+    for (int t = 0; t < NM; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int i, cc;
+        out_pos(c0, t, r, i, cc);
+        const TO v = (TO)acc[t][r];
+        if constexpr (DOT) dsum += (double)v * dv[t * 4 + r];
+        if (cc < ncols && i < n) Y[(size_t)column_base(cc) + (size_t)i * L] = v;
+      }
+  }
+  if constexpr (DOT) {
     const double s = block_sum(dsum, red);
     if (tid == 0) partials[blockIdx.x] = s;
   }
 }
 
-template <typename TC, typename TI, typename TO>
-static int launch_fd_mode(stls_ctx* h, const TI* X, TO* Y, int L, int n, int ncols, const TC* A, int npad,
-                          int fused, const TC* A2, const double* lam_t, const double* dotv,
-                          double* partials, int* nparts) {
+template <typename TC, typename TI, typename TO, bool TRANS, bool FUSED, bool DOT>
+using FdKernelPtr = void (*)(const TI*, TO*, int, int, int, const TC*, const TC*, int, const double*, const double*,
+                             const double*, double*);
+
+template <typename TC, typename TI, typename TO, bool TRANS, bool FUSED, bool DOT, int NM>
+static FdKernelPtr<TC, TI, TO, TRANS, FUSED, DOT> fd_pick(bool wlds) {
+  if constexpr (NM <= 8) {
+    if (wlds) return fd_mode_kernel<TC, TI, TO, NM, TRANS, true, FUSED, DOT>;
+  }
+  return fd_mode_kernel<TC, TI, TO, NM, TRANS, false, FUSED, DOT>;
+}
+
+// One mode product (or the fused time kernel) over the (L, n, R) view.
+// TRANS: contiguous mode (L == 1); FUSED: time kernel with A2 = backward
+// operand; DOT: also write partial sums of Y . dotv.
+template <typename TC, typename TI, typename TO, bool TRANS, bool FUSED, bool DOT>
+static int launch_fd_mode(stls_ctx* h, const TI* X, TO* Y, int L, int n, int ncols, const TC* A, const TC* A2,
+                          int npad, const double* lam_t, const double* dotv, double* partials, int* nparts) {
   const int nm = npad / 16;
-  const int blocks = (ncols + kCols - 1) / kCols;
-  const size_t shmem = sizeof(TC) * (size_t)npad * kLdx + sizeof(int) * kCols + 4 * sizeof(double);
-  if (dotv && blocks > kPartialsCap) { set_error("too many partial sums"); return STLS_EINVAL; }
+  const int npanels = (ncols + kCols - 1) / kCols;
+  const size_t tail = sizeof(TC) * (size_t)npad * kLdx + 4 * sizeof(double);
+  const size_t wbytes = sizeof(TC) * (size_t)npad * (npad + 16);
+  // W in LDS only while two or more workgroups still fit on a CU
+  const bool wlds = nm <= 8 && wbytes + tail <= 64 * 1024;
+  const bool w2lds = FUSED && wlds && 2 * wbytes + tail <= 80 * 1024;
+  const size_t shmem = (wlds ? wbytes : 0) + (w2lds ? wbytes : 0) + tail;
+  if (shmem > 160 * 1024) { set_error("direction too large for the FD kernel's LDS budget"); return STLS_EINVAL; }
+  const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / shmem)));
+  const int blocks = std::min(npanels, 256 * per_cu);
+  if (DOT && blocks > kPartialsCap) { set_error("too many partial sums"); return STLS_EINVAL; }
   if (nparts) *nparts = blocks;
-  prof_begin(h);
-#define STLS_FD_CASE(NMV)                                                                          \
-  case NMV:                                                                                        \
-    kern = fd_mode_kernel<TC, TI, TO, NMV>;                                                        \
-    break;
-  void (*kern)(const TI*, TO*, int, int, int, const TC*, int, int, const TC*, const double*, const double*,
-               const double*, double*) = nullptr;
+  FdKernelPtr<TC, TI, TO, TRANS, FUSED, DOT> kern = nullptr;
+#define STLS_FD_PICK(NMV) \
+  case NMV: kern = fd_pick<TC, TI, TO, TRANS, FUSED, DOT, NMV>(wlds); break;
   switch (nm) {
-    STLS_FD_CASE(1) STLS_FD_CASE(2) STLS_FD_CASE(3) STLS_FD_CASE(4) STLS_FD_CASE(5) STLS_FD_CASE(6)
-    STLS_FD_CASE(7) STLS_FD_CASE(8) STLS_FD_CASE(9) STLS_FD_CASE(10) STLS_FD_CASE(11) STLS_FD_CASE(12)
-    STLS_FD_CASE(13) STLS_FD_CASE(14) STLS_FD_CASE(15) STLS_FD_CASE(16)
+    STLS_FD_PICK(1) STLS_FD_PICK(2) STLS_FD_PICK(3) STLS_FD_PICK(4) STLS_FD_PICK(5) STLS_FD_PICK(6)
+    STLS_FD_PICK(7) STLS_FD_PICK(8) STLS_FD_PICK(9) STLS_FD_PICK(10) STLS_FD_PICK(11) STLS_FD_PICK(12)
+    STLS_FD_PICK(13) STLS_FD_PICK(14) STLS_FD_PICK(15) STLS_FD_PICK(16)
     default: set_error("direction too large for the FD kernel"); return STLS_EINVAL;
   }
+#undef STLS_FD_PICK
   if (shmem > 65536) {
     hipError_t ea = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (ea != hipSuccess) return hip_fail(ea, "hipFuncSetAttribute(LDS)");
   }
-  hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), shmem, h->stream, X, Y, L, n, ncols, A, npad, fused, A2,
-                     lam_t, h->lam_s, dotv, partials);
-#undef STLS_FD_CASE
+  prof_begin(h);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), shmem, h->stream, X, Y, L, n, ncols, A, A2, (int)w2lds, lam_t,
+                     h->lam_s, dotv, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "fd_mode_kernel launch");
-  prof_end(h, fused ? PROF_FD_TIME : PROF_FD_SPACE);
+  prof_end(h, FUSED ? PROF_FD_TIME : PROF_FD_SPACE);
   return STLS_OK;
 }
 
@@ -215,37 +344,39 @@ static int prec_apply_t(stls_ctx* h, const double* r, double* s, const double* d
   };
   int st;
   int cur = 0;
-  // forward chain over space modes 1..d: r -> buf
   int L = 1;
   for (int k = 0; k < d; ++k) {
     const int n = h->dir[k].n;
     const int ncols = (int)(h->ndof / n);
-    if (k == 0) st = launch_fd_mode<TC, double, TC>(h, r, buf[cur], L, n, ncols, fwdA(k), h->dd[k].npad, 0,
-                                                    nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (k == 0)
+      st = launch_fd_mode<TC, double, TC, true, false, false>(h, r, buf[cur], L, n, ncols, fwdA(k), nullptr,
+                                                              h->dd[k].npad, nullptr, nullptr, nullptr, nullptr);
     else {
-      st = launch_fd_mode<TC, TC, TC>(h, buf[cur], buf[cur ^ 1], L, n, ncols, fwdA(k), h->dd[k].npad, 0,
-                                      nullptr, nullptr, nullptr, nullptr, nullptr);
+      st = launch_fd_mode<TC, TC, TC, false, false, false>(h, buf[cur], buf[cur ^ 1], L, n, ncols, fwdA(k), nullptr,
+                                                           h->dd[k].npad, nullptr, nullptr, nullptr, nullptr);
       cur ^= 1;
     }
     if (st) return st;
     L *= n;
   }
-  // time: forward product, division, backward product
-  st = launch_fd_mode<TC, TC, TC>(h, buf[cur], buf[cur ^ 1], ns, nt, ns, fwdA(d), h->dd[d].npad, 1,
-                                  bwdA(d), h->dd[d].lam, nullptr, nullptr, nullptr);
+  st = launch_fd_mode<TC, TC, TC, false, true, false>(h, buf[cur], buf[cur ^ 1], ns, nt, ns, fwdA(d), bwdA(d),
+                                                      h->dd[d].npad, h->dd[d].lam, nullptr, nullptr, nullptr);
   if (st) return st;
   cur ^= 1;
-  // backward chain over space modes d..1
   for (int k = d - 1; k >= 0; --k) {
     const int n = h->dir[k].n;
     L /= n;
     const int ncols = (int)(h->ndof / n);
     if (k == 0)
-      st = launch_fd_mode<TC, TC, double>(h, buf[cur], s, L, n, ncols, bwdA(k), h->dd[k].npad, 0, nullptr,
-                                          nullptr, dot_with, partials, nparts);
+      st = dot_with ? launch_fd_mode<TC, TC, double, true, false, true>(h, buf[cur], s, L, n, ncols, bwdA(k), nullptr,
+                                                                        h->dd[k].npad, nullptr, dot_with, partials,
+                                                                        nparts)
+                    : launch_fd_mode<TC, TC, double, true, false, false>(h, buf[cur], s, L, n, ncols, bwdA(k),
+                                                                         nullptr, h->dd[k].npad, nullptr, nullptr,
+                                                                         nullptr, nparts);
     else {
-      st = launch_fd_mode<TC, TC, TC>(h, buf[cur], buf[cur ^ 1], L, n, ncols, bwdA(k), h->dd[k].npad, 0,
-                                      nullptr, nullptr, nullptr, nullptr, nullptr);
+      st = launch_fd_mode<TC, TC, TC, false, false, false>(h, buf[cur], buf[cur ^ 1], L, n, ncols, bwdA(k), nullptr,
+                                                           h->dd[k].npad, nullptr, nullptr, nullptr, nullptr);
       cur ^= 1;
     }
     if (st) return st;
@@ -263,173 +394,465 @@ int launch_prec_apply(stls_ctx* h, const double* r, double* s, const double* dot
 }
 
 // ---------------------------------------------------------------------------
-// Banded mode products of the matvec.  Each output is a short sum of terms
-// coef * B_t (in_s) along one mode, B_t a banded univariate matrix stored
-// n x (2p+1) row-major.  One thread per output entry; the band neighbours of
-// an entry are L apart, so consecutive threads read consecutive addresses.
-struct BandTerm {
-  int in;      // input slot
-  int band;    // band matrix slot
-  double coef;
-};
-struct BandProg {
-  const double* in[3];
-  double* out[3];
-  const double* band[3];
-  int nin, nout;
-  int nterm[3];
-  BandTerm term[3][4];
-  const double* last_add;  // optional: out[0](l, n-1) += last_add[l] (R must be 1)
-  const double* dotv;      // optional: partial sums of out[0] .* dotv
-  double* partials;
-};
-
-__global__ __launch_bounds__(kThreads) void band_mode_kernel(BandProg P, int L, int n, int total, int p) {
-  __shared__ double red[4];
-  const int bw = 2 * p + 1;
-  double dsum = 0.0;
-  for (int e = blockIdx.x * kThreads + threadIdx.x; e < total; e += gridDim.x * kThreads) {
-    const int l = e % L;
-    const int rest = e / L;
-    const int i = rest % n;
-    const int r = rest / n;
-    const size_t base = (size_t)l + (size_t)r * L * n;
-    double acc[3] = {0.0, 0.0, 0.0};
-    const int jlo = max(0, i - p), jhi = min(n - 1, i + p);
-    for (int j = jlo; j <= jhi; ++j) {
-      double v[3];
-      for (int s = 0; s < P.nin; ++s) v[s] = P.in[s][base + (size_t)j * L];
-      const int o = j - i + p;
-      for (int q = 0; q < P.nout; ++q)
-        for (int t = 0; t < P.nterm[q]; ++t) {
-          const BandTerm& T = P.term[q][t];
-          acc[q] += T.coef * P.band[T.band][i * bw + o] * v[T.in];
-        }
-    }
-    if (P.last_add && i == n - 1) acc[0] += P.last_add[l];
-    for (int q = 0; q < P.nout; ++q) P.out[q][e] = acc[q];
-    if (P.dotv) dsum += acc[0] * P.dotv[e];
-  }
-  if (P.dotv) {
-    const double s = block_sum(dsum, red);
-    if (threadIdx.x == 0) P.partials[blockIdx.x] = s;
-  }
-}
-
-static int launch_band(stls_ctx* h, const BandProg& P, int L, int n, int total, int p, int prof_id,
-                       int* nparts) {
-  int blocks = (total + kThreads - 1) / kThreads;
-  blocks = std::min(blocks, kMaxBlocksEW);
-  if (nparts) *nparts = blocks;
-  prof_begin(h);
-  hipLaunchKernelGGL(band_mode_kernel, dim3(blocks), dim3(kThreads), 0, h->stream, P, L, n, total, p);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "band_mode_kernel launch");
-  prof_end(h, prof_id);
-  return STLS_OK;
-}
-
-// y = (K_t x M_s + kappa^2 M_t x J_s + kappa W_t x L_s) x on the unit box.
-// On the Dirichlet-restricted space int b_i'' b_j = -int b_i' b_j', so the
-// mixed second-derivative terms of J_s are K_k x K_l and
+// Matrix-free matvec y = (K_t x M_s + kappa^2 M_t x J_s + kappa W_t x L_s) x
+// on the unit box (§4.1 eq. A_kron with the diffusivity).  On the
+// Dirichlet-restricted space int b_i'' b_j = -int b_i' b_j', so the mixed
+// second-derivative terms of J_s are K_k x K_l:
 //   J_s = sum_k (J_k, M elsewhere) + 2 sum_{k<l} (K_k, K_l, M elsewhere),
 //   L_s = sum_k (K_k, M elsewhere).
-// Grouping by the operator of the last space direction d:
-//   A = (M..M) x,  B = [J_s inner part] x,  C = [L_s inner part] x  over modes < d,
-//   S1 = M_d A,  S2 = kappa^2 (J_d A + M_d B + 2 K_d C),  S3 = kappa w (K_d A + M_d C) at t = T,
-//   y = K_t S1 + M_t S2 + e_T (x) S3.
+// Grouped by the operator of the last space direction d and time:
+//   inner (directions < d):  A = (M..M) x,  B = (J_s part of dirs < d) x,
+//                            C = (L_s part of dirs < d) x
+//   outer ((i_d, t) plane):  S1 = M_d A,  S2 = kappa^2 (J_d A + M_d B + 2 K_d C),
+//                            y  = K_t S1 + M_t S2 + e_T (x) kappa w (K_d A + M_d C)
+// d = 1 has no inner stage (A = x, B = C = 0).  Banded factors are stored
+// n x (2p+1) row-major, zero outside the matrix.
+
+// Inner stage, d = 2: banded products along contiguous columns of n1.
+constexpr int kInnerChunk = 1024;
+__global__ __launch_bounds__(kThreads) void mv_inner1_kernel(const double* __restrict__ x, double* __restrict__ A,
+                                                             double* __restrict__ B, double* __restrict__ C, int n1,
+                                                             int N, int p, const double* __restrict__ Mb,
+                                                             const double* __restrict__ Jb,
+                                                             const double* __restrict__ Kb) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int bw = 2 * p + 1;
+  double* xs = reinterpret_cast<double*>(smem_raw);
+  double* bM = xs + kInnerChunk + 2 * p;
+  double* bJ = bM + n1 * bw;
+  double* bK = bJ + n1 * bw;
+  for (int t = threadIdx.x; t < n1 * bw; t += kThreads) { bM[t] = Mb[t]; bJ[t] = Jb[t]; bK[t] = Kb[t]; }
+  const int nchunks = (N + kInnerChunk - 1) / kInnerChunk;
+  for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const int e0 = ch * kInnerChunk;
+    __syncthreads();
+    for (int t = threadIdx.x; t < kInnerChunk + 2 * p; t += kThreads) {
+      const int g = e0 - p + t;
+      xs[t] = (g >= 0 && g < N) ? x[g] : 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kInnerChunk; t += kThreads) {
+      const int e = e0 + t;
+      if (e >= N) break;
+      const int i = e % n1;
+      double a = 0.0, b = 0.0, c = 0.0;
+      for (int o = 0; o < bw; ++o) {
+        const int j = i + o - p;
+        if (j < 0 || j >= n1) continue;
+        const double v = xs[t + o];
+        a += bM[i * bw + o] * v;
+        b += bJ[i * bw + o] * v;
+        c += bK[i * bw + o] * v;
+      }
+      A[e] = a;
+      B[e] = b;
+      C[e] = c;
+    }
+  }
+}
+
+// Inner stage, d = 3: one workgroup per (i3, t) slab and chunk of T2 rows in
+// i2; direction-1 products for the rows of the chunk plus a halo of p2 rows,
+// then direction-2 products:
+//   A = M2 (M1 x),  B = J2 (M1 x) + M2 (J1 x) + 2 K2 (K1 x),  C = K2 (M1 x) + M2 (K1 x)
+// Lanes run along i1 (contiguous), the four waves along rows.  P > 0: both
+// degrees equal P, direction-1 band rows live in registers; P = 0: runtime
+// degrees.  Row indices are wave-uniform, so direction-2 coefficients come
+// through scalar loads.
+constexpr int kInnerPf = 8;
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void mv_inner12_kernel(
+    const double* __restrict__ x, double* __restrict__ A, double* __restrict__ B, double* __restrict__ C, int n1,
+    int n2, int T2, int ntile2, int nwork, int p1r, int p2r, const double* __restrict__ M1,
+    const double* __restrict__ J1, const double* __restrict__ K1, const double* __restrict__ M2,
+    const double* __restrict__ J2, const double* __restrict__ K2) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int p1 = P > 0 ? P : p1r, p2 = P > 0 ? P : p2r;
+  const int bw1 = 2 * p1 + 1, bw2 = 2 * p2 + 1;
+  const int hmax = min(n2, T2 + 2 * p2);
+  double* xs = reinterpret_cast<double*>(smem_raw);  // hmax x n1
+  double* XM = xs + hmax * n1;
+  double* XJ = XM + hmax * n1;
+  double* XK = XJ + hmax * n1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int BW = P > 0 ? 2 * P + 1 : 1;
+  double cM[BW], cJ[BW], cK[BW];
+  // The chunk of x of the next work item is fetched into registers while the
+  // current one is processed (hmax * n1 <= kInnerPf * kThreads by the LDS budget).
+  double pf[kInnerPf];
+  auto fetch = [&](int wi_) {
+    const int w_ = xcd_tile(wi_, nwork);
+    const int slab_ = w_ / ntile2, tile_ = w_ - slab_ * ntile2;
+    const int r0_ = tile_ * T2, r1_ = min(n2, r0_ + T2);
+    const int h0_ = max(0, r0_ - p2), nh_ = min(n2, r1_ + p2) - h0_;
+    const size_t off = (size_t)slab_ * n1 * n2 + (size_t)h0_ * n1;
+#pragma unroll
+    for (int s = 0; s < kInnerPf; ++s) {
+      const int t = threadIdx.x + kThreads * s;
+      const bool ok = t < nh_ * n1;
+      const double v = x[off + (ok ? t : 0)];
+      pf[s] = ok ? v : 0.0;
+    }
+  };
+  if (blockIdx.x < nwork) fetch(blockIdx.x);
+  for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
+    const int w = xcd_tile(wi, nwork);
+    const int slab = w / ntile2, tile = w - slab * ntile2;
+    const int r0 = tile * T2, r1 = min(n2, r0 + T2);
+    const int h0 = max(0, r0 - p2), h1 = min(n2, r1 + p2), nh = h1 - h0;
+    const size_t base = (size_t)slab * n1 * n2;
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kInnerPf; ++s) {
+      const int t = threadIdx.x + kThreads * s;
+      if (t < nh * n1) xs[t] = pf[s];
+    }
+    __syncthreads();
+    if (wi + (int)gridDim.x < nwork) fetch(wi + gridDim.x);
+    for (int i1 = lane; i1 < n1; i1 += 64) {
+      if constexpr (P > 0) {
+#pragma unroll
+        for (int o = 0; o < BW; ++o) {
+          cM[o] = M1[i1 * BW + o]; cJ[o] = J1[i1 * BW + o]; cK[o] = K1[i1 * BW + o];
+        }
+      }
+      for (int row = wave; row < nh; row += kThreads / 64) {
+        double m = 0.0, jj = 0.0, kk = 0.0;
+        if constexpr (P > 0) {
+#pragma unroll
+          for (int o = 0; o < BW; ++o) {
+            // band entries outside the matrix are stored as zeros: clamp the
+            // column so that every LDS read stays inside the slab
+            const int j = min(max(i1 + o - P, 0), n1 - 1);
+            const double v = xs[row * n1 + j];
+            m += cM[o] * v; jj += cJ[o] * v; kk += cK[o] * v;
+          }
+        } else {
+          for (int o = 0; o < bw1; ++o) {
+            const int j = i1 + o - p1;
+            if (j < 0 || j >= n1) continue;
+            const double v = xs[row * n1 + j];
+            m += M1[i1 * bw1 + o] * v; jj += J1[i1 * bw1 + o] * v; kk += K1[i1 * bw1 + o] * v;
+          }
+        }
+        XM[row * n1 + i1] = m;
+        XJ[row * n1 + i1] = jj;
+        XK[row * n1 + i1] = kk;
+      }
+    }
+    __syncthreads();
+    for (int rr = wave; rr < r1 - r0; rr += kThreads / 64) {
+      const int i2 = __builtin_amdgcn_readfirstlane(r0 + rr);  // wave-uniform row
+      for (int i1 = lane; i1 < n1; i1 += 64) {
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int o = 0; o < bw2; ++o) {
+          const int j2 = i2 + o - p2;
+          if (j2 < 0 || j2 >= n2) continue;
+          const int hr = (j2 - h0) * n1 + i1;
+          const double m = XM[hr], jv = XJ[hr], kv = XK[hr];
+          const double cm = M2[i2 * bw2 + o], cj = J2[i2 * bw2 + o], ck = K2[i2 * bw2 + o];
+          a += cm * m;
+          b += cj * m + cm * jv + 2.0 * ck * kv;
+          c += ck * m + cm * kv;
+        }
+        const size_t g = base + (size_t)i2 * n1 + i1;
+        A[g] = a;
+        B[g] = b;
+        C[g] = c;
+      }
+    }
+  }
+}
+
+// Outer stage.  A workgroup owns 16 consecutive inner indices l (one 128-byte
+// run per row) x Td rows of i_d x a chunk [c0, c1) of output time slices.  It
+// streams the input slices t in [c0 - PT, c1 + PT): slice t + 2 is being
+// loaded into registers while slice t + 1 waits in LDS and slice t is
+// processed (3-slot LDS ring).  Every thread keeps for its (l, i_d) pencil a
+// window of S1, S2 over 2 PT + 1 slices and emits
+//   y(t') = sum_k K_t(t', t'-PT+k) S1w[k] + M_t(t', t'-PT+k) S2w[k]
+// once slice t' + PT is in.  The final-time term and the partial dot product
+// y . dotv are fused.  PD > 0: space degree PD known at compile time (band
+// rows of the thread's i_d in registers); PD = 0: runtime space degree.
+constexpr int kOuterLb = 16;             // inner indices per workgroup
+constexpr int kOuterLds = kOuterLb;      // LDS row: 16 doubles, two rows per half wave fill the banks
+constexpr int kOuterMaxTd = 16;
+constexpr int kOuterSlots = 2;           // staged rows per thread and input: rows <= 32
+
+template <int PT, int PD, bool THREE, bool DOT>
+__global__ __launch_bounds__(kThreads) void mv_outer_kernel(
+    const double* __restrict__ A, const double* __restrict__ B, const double* __restrict__ C, double* __restrict__ y,
+    int L, int nd, int nt, int pdr, int Td, int nlb, int ntd, int nchunk, int Tc, const double* __restrict__ Md,
+    const double* __restrict__ Jd, const double* __restrict__ Kd, const double* __restrict__ Kt,
+    const double* __restrict__ Mt, double k2, double kw, const double* __restrict__ dotv,
+    double* __restrict__ partials) {
+  constexpr int W = 2 * PT + 1;
+  constexpr int BWD = PD > 0 ? 2 * PD + 1 : 1;
+  constexpr int NQ = THREE ? 3 : 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[4];
+  const int pd = PD > 0 ? PD : pdr;
+  const int bwd = 2 * pd + 1;
+  const int rows = Td + 2 * pd;
+  double* bands = reinterpret_cast<double*>(smem_raw);  // Md | Jd | Kd, nd x bwd each (PD == 0)
+  double* sbuf = bands + (PD > 0 ? 0 : 3 * nd * bwd);    // 3 slots x (NQ x rows x kOuterLds)
+  const int buf_stride = NQ * rows * kOuterLds;
+  if (PD == 0)
+    for (int t = threadIdx.x; t < nd * bwd; t += kThreads) {
+      bands[t] = Md[t]; bands[nd * bwd + t] = Jd[t]; bands[2 * nd * bwd + t] = Kd[t];
+    }
+  const int ntile = nlb * ntd * nchunk;
+  const int tile = xcd_tile(blockIdx.x, ntile);
+  const int td = tile % ntd;
+  const int lb = (tile / ntd) % nlb;
+  const int ch = tile / (ntd * nlb);
+  const int l0 = lb * kOuterLb, d0 = td * Td;
+  const int c0 = ch * Tc, c1 = min(nt, c0 + Tc);
+  const int li = threadIdx.x % kOuterLb, di = threadIdx.x / kOuterLb;
+  const int l = l0 + li, id = d0 + di;
+  const bool mine = (di < Td) && (l < L) && (id < nd);
+  // clamped coordinates: threads outside the tile compute on valid data and
+  // their results are discarded, so the loop has no divergent branches
+  const int dic = min(di, Td - 1), idc = min(id, nd - 1), lc = min(l, L - 1);
+  const size_t plane = (size_t)L * nd;  // one time slice
+
+  // staging coordinates of this thread: lane li, staged rows di + 16 s
+  int soff[kOuterSlots];
+  bool sok[kOuterSlots];
+#pragma unroll
+  for (int s = 0; s < kOuterSlots; ++s) {
+    const int rr = di + kOuterMaxTd * s;
+    const int row = d0 - pd + rr;
+    sok[s] = rr < rows && row >= 0 && row < nd && l < L;
+    soff[s] = sok[s] ? row * L + l : 0;
+  }
+  double cm[BWD], cj[BWD], ck[BWD];
+  if constexpr (PD > 0) {
+#pragma unroll
+    for (int o = 0; o < BWD; ++o) {
+      cm[o] = Md[idc * BWD + o];
+      cj[o] = Jd[idc * BWD + o];
+      ck[o] = Kd[idc * BWD + o];
+    }
+  }
+  auto load_slice = [&](int t, double (&regs)[NQ][kOuterSlots]) {
+    const size_t tb0 = (size_t)t * plane;
+#pragma unroll
+    for (int s = 0; s < kOuterSlots; ++s) {
+      const size_t g = tb0 + soff[s];
+      const double a = A[g];
+      regs[0][s] = sok[s] ? a : 0.0;
+      if constexpr (THREE) {
+        const double bv = B[g], cv = C[g];
+        regs[1][s] = sok[s] ? bv : 0.0;
+        regs[2][s] = sok[s] ? cv : 0.0;
+      }
+    }
+  };
+  auto park_slice = [&](const double (&regs)[NQ][kOuterSlots], double* buf) {
+#pragma unroll
+    for (int s = 0; s < kOuterSlots; ++s) {
+      const int rr = di + kOuterMaxTd * s;
+      if (rr < rows) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) buf[q * rows * kOuterLds + rr * kOuterLds + li] = regs[q][s];
+      }
+    }
+  };
+
+  double S1w[W], S2w[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) { S1w[k] = 0.0; S2w[k] = 0.0; }
+  double S3 = 0.0, dsum = 0.0;
+  const int tb = max(0, c0 - PT);   // first input slice (tb < nt)
+  const int te = c1 - 1 + PT;       // last window position (inputs beyond nt are zero)
+  const int tl = min(te, nt - 1);   // last input slice
+  double ra[NQ][kOuterSlots], rb[NQ][kOuterSlots];
+  load_slice(tb, ra);
+  __syncthreads();  // bands in LDS
+  park_slice(ra, sbuf);
+  load_slice(min(tb + 1, tl), ra);
+  __syncthreads();
+  // One input slice: prefetch slice t + 2 into `nxt`, process slice t from
+  // LDS, park slice t + 1 (held in `cur`).  The loop is unrolled by two with
+  // the register sets swapped so that no copy forces an early wait.
+  auto step = [&](int t, double (&nxt)[NQ][kOuterSlots], double (&cur)[NQ][kOuterSlots]) {
+    const int tp = t - PT;  // output slice completed by this input
+    // operand of the fused dot product, requested before the slice prefetch
+    double dvv = 0.0;
+    const size_t gout = (size_t)max(tp, 0) * plane + (size_t)idc * L + lc;
+    if constexpr (DOT) dvv = dotv[gout];
+    load_slice(min(t + 2, tl), nxt);  // unconditional: a repeated load at the end is harmless
+    const double* buf = sbuf + ((t - tb) % 3) * buf_stride;
+    double s1 = 0.0, jA = 0.0, mB = 0.0, kC = 0.0;
+    auto tap = [&](int o, double m_, double j_, double k_) {
+      const int rr = dic + o;  // staged row of i_d + o - pd
+      const double a = buf[rr * kOuterLds + li];
+      s1 += m_ * a;
+      jA += j_ * a;
+      if constexpr (THREE) {
+        mB += m_ * buf[rows * kOuterLds + rr * kOuterLds + li];
+        kC += k_ * buf[2 * rows * kOuterLds + rr * kOuterLds + li];
+      }
+    };
+    if constexpr (PD > 0) {
+#pragma unroll
+      for (int o = 0; o < BWD; ++o) tap(o, cm[o], cj[o], ck[o]);
+    } else {
+      for (int o = 0; o < bwd; ++o)
+        tap(o, bands[idc * bwd + o], bands[nd * bwd + idc * bwd + o], bands[2 * nd * bwd + idc * bwd + o]);
+    }
+    const bool have = t < nt;
+    double s2 = k2 * (jA + mB + 2.0 * kC);
+    s1 = have ? s1 : 0.0;
+    s2 = have ? s2 : 0.0;
+    if (t == nt - 1) {  // final-time term kappa w (K_d A + M_d C) (uniform branch, LDS only)
+      double kA = 0.0, mC = 0.0;
+      if constexpr (PD > 0) {
+#pragma unroll
+        for (int o = 0; o < BWD; ++o) {
+          kA += ck[o] * buf[(dic + o) * kOuterLds + li];
+          if constexpr (THREE) mC += cm[o] * buf[2 * rows * kOuterLds + (dic + o) * kOuterLds + li];
+        }
+      } else {
+        for (int o = 0; o < bwd; ++o) {
+          kA += bands[2 * nd * bwd + idc * bwd + o] * buf[(dic + o) * kOuterLds + li];
+          if constexpr (THREE) mC += bands[idc * bwd + o] * buf[2 * rows * kOuterLds + (dic + o) * kOuterLds + li];
+        }
+      }
+      S3 = kw * (kA + mC);
+    }
+#pragma unroll
+    for (int k = 0; k < W - 1; ++k) { S1w[k] = S1w[k + 1]; S2w[k] = S2w[k + 1]; }
+    S1w[W - 1] = s1;
+    S2w[W - 1] = s2;
+    if (tp >= c0 && tp < c1) {  // uniform
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < W; ++k) v += Kt[tp * W + k] * S1w[k] + Mt[tp * W + k] * S2w[k];
+      if (tp == nt - 1) v += S3;
+      if constexpr (DOT) dsum += mine ? v * dvv : 0.0;
+      if (mine) y[gout] = v;
+    }
+    park_slice(cur, sbuf + ((t + 1 - tb) % 3) * buf_stride);
+    __syncthreads();
+  };
+  for (int t = tb; t <= te; t += 2) {
+    step(t, rb, ra);
+    if (t + 1 <= te) step(t + 1, ra, rb);
+  }
+  if constexpr (DOT) {
+    const double s = block_sum(dsum, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  }
+}
+
 int launch_matvec(stls_ctx* h, const double* x, double* y, const double* dot_with, double* partials,
                   int* nparts) {
   const int d = h->d;
   const int N = (int)h->ndof;
-  const double k2 = h->kappa * h->kappa;
   double** w = h->work;
   const double* A = x;
   const double* B = nullptr;
   const double* C = nullptr;
-  int st;
+  hipError_t e;
   int L = 1;
-  if (d >= 2) {
-    // mode 1: XM = M1 x, XJ = J1 x, XK = K1 x
+  if (d == 2) {
     const DevDir& D1 = h->dd[0];
-    BandProg P{};
-    P.in[0] = x;
-    P.nin = 1;
-    P.band[0] = D1.M; P.band[1] = D1.J; P.band[2] = D1.K;
-    P.nout = 3;
-    P.out[0] = w[0]; P.out[1] = w[1]; P.out[2] = w[2];
-    for (int q = 0; q < 3; ++q) { P.nterm[q] = 1; P.term[q][0] = {0, q, 1.0}; }
-    if ((st = launch_band(h, P, 1, D1.n, N, D1.p, PROF_MV_INNER1, nullptr))) return st;
+    const int bw = 2 * D1.p + 1;
+    const size_t shmem = sizeof(double) * (kInnerChunk + 2 * D1.p + 3 * (size_t)D1.n * bw);
+    const int chunks = (N + kInnerChunk - 1) / kInnerChunk;
+    const int blocks = std::min(chunks, 256 * 8);
+    prof_begin(h);
+    hipLaunchKernelGGL(mv_inner1_kernel, dim3(blocks), dim3(kThreads), shmem, h->stream, x, w[0], w[1], w[2], D1.n,
+                       N, D1.p, D1.M, D1.J, D1.K);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "mv_inner1_kernel launch");
+    prof_end(h, PROF_MV_INNER1);
+    A = w[0]; B = w[1]; C = w[2];
     L = D1.n;
-    if (d == 2) {
-      A = w[0]; B = w[1]; C = w[2];
-    } else {
-      // mode 2: A = M2 XM, B = J2 XM + M2 XJ + 2 K2 XK, C = K2 XM + M2 XK
-      const DevDir& D2 = h->dd[1];
-      BandProg Q{};
-      Q.in[0] = w[0]; Q.in[1] = w[1]; Q.in[2] = w[2];
-      Q.nin = 3;
-      Q.band[0] = D2.M; Q.band[1] = D2.J; Q.band[2] = D2.K;
-      Q.nout = 3;
-      Q.out[0] = w[3]; Q.out[1] = w[4]; Q.out[2] = w[5];
-      Q.nterm[0] = 1; Q.term[0][0] = {0, 0, 1.0};
-      Q.nterm[1] = 3; Q.term[1][0] = {0, 1, 1.0}; Q.term[1][1] = {1, 0, 1.0}; Q.term[1][2] = {2, 2, 2.0};
-      Q.nterm[2] = 2; Q.term[2][0] = {0, 2, 1.0}; Q.term[2][1] = {2, 0, 1.0};
-      if ((st = launch_band(h, Q, L, D2.n, N, D2.p, PROF_MV_INNER2, nullptr))) return st;
-      L *= D2.n;
-      A = w[3]; B = w[4]; C = w[5];
+  } else if (d == 3) {
+    const DevDir& D1 = h->dd[0];
+    const DevDir& D2 = h->dd[1];
+    const int n1 = D1.n, n2 = D2.n;
+    const size_t budget = 64 * 1024;
+    int T2 = n2;
+    auto lds_for = [&](int t2) { return sizeof(double) * 4 * (size_t)std::min(n2, t2 + 2 * D2.p) * n1; };
+    auto fits = [&](int t2) {
+      return lds_for(t2) <= budget && (size_t)std::min(n2, t2 + 2 * D2.p) * n1 <= (size_t)kInnerPf * kThreads;
+    };
+    while (T2 > 1 && !fits(T2)) --T2;
+    if (!fits(T2)) { set_error("space direction too large for the matvec kernel"); return STLS_EINVAL; }
+    const int ntile = (n2 + T2 - 1) / T2;
+    T2 = (n2 + ntile - 1) / ntile;
+    const size_t shmem = lds_for(T2);
+    const int nwork = ntile * (N / (n1 * n2));
+    const int blocks = std::min(nwork, 256 * 8);
+    const int P = (D1.p == D2.p) ? D1.p : 0;
+    void (*kern)(const double*, double*, double*, double*, int, int, int, int, int, int, int, const double*,
+                 const double*, const double*, const double*, const double*, const double*) = nullptr;
+    switch (P) {
+      case 2: kern = mv_inner12_kernel<2>; break;
+      case 3: kern = mv_inner12_kernel<3>; break;
+      case 4: kern = mv_inner12_kernel<4>; break;
+      case 5: kern = mv_inner12_kernel<5>; break;
+      case 6: kern = mv_inner12_kernel<6>; break;
+      default: kern = mv_inner12_kernel<0>; break;
     }
+    if (shmem > 65536) {
+      e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+      if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(LDS)");
+    }
+    prof_begin(h);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), shmem, h->stream, x, w[0], w[1], w[2], n1, n2, T2, ntile,
+                       nwork, D1.p, D2.p, D1.M, D1.J, D1.K, D2.M, D2.J, D2.K);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "mv_inner12_kernel launch");
+    prof_end(h, PROF_MV_INNER2);
+    A = w[0]; B = w[1]; C = w[2];
+    L = n1 * n2;
   }
-  // last space mode d: S1, S2 over all time slices, S3 on the final slice
   const DevDir& Dd = h->dd[d - 1];
   const DevDir& Dt = h->dd[d];
-  const int nt = Dt.n;
-  double* S1 = (d == 3) ? w[0] : (d == 2 ? w[3] : w[0]);
-  double* S2 = (d == 3) ? w[1] : (d == 2 ? w[4] : w[1]);
-  double* S3 = h->fdbuf[0];  // ns entries are enough
-  {
-    BandProg P{};
-    P.in[0] = A; P.in[1] = B; P.in[2] = C;
-    P.nin = B ? 3 : 1;
-    P.band[0] = Dd.M; P.band[1] = Dd.J; P.band[2] = Dd.K;
-    P.nout = 2;
-    P.out[0] = S1; P.out[1] = S2;
-    P.nterm[0] = 1; P.term[0][0] = {0, 0, 1.0};
-    if (B) {
-      P.nterm[1] = 3; P.term[1][0] = {0, 1, k2}; P.term[1][1] = {1, 0, k2}; P.term[1][2] = {2, 2, 2.0 * k2};
-    } else {
-      P.nterm[1] = 1; P.term[1][0] = {0, 1, k2};
-    }
-    if ((st = launch_band(h, P, L, Dd.n, N, Dd.p, PROF_MV_SPACE, nullptr))) return st;
-    // final-time slice: S3 = kappa w (K_d A + M_d C)
-    const size_t last = (size_t)(nt - 1) * h->ns;
-    BandProg Q{};
-    Q.in[0] = A + last;
-    Q.in[1] = C ? C + last : nullptr;
-    Q.nin = C ? 2 : 1;
-    Q.band[0] = Dd.K; Q.band[1] = Dd.M;
-    Q.nout = 1;
-    Q.out[0] = S3;
-    const double kw = h->kappa * h->dir[d].wend;
-    Q.nterm[0] = C ? 2 : 1;
-    Q.term[0][0] = {0, 0, kw};
-    if (C) Q.term[0][1] = {1, 1, kw};
-    if ((st = launch_band(h, Q, L, Dd.n, (int)h->ns, Dd.p, PROF_MV_LAST, nullptr))) return st;
+  const int nd = Dd.n, nt = Dt.n, pd = Dd.p;
+  const int ntd = (nd + kOuterMaxTd - 1) / kOuterMaxTd;
+  const int Td = (nd + ntd - 1) / ntd;
+  const int nlb = (L + kOuterLb - 1) / kOuterLb;
+  const int rows = Td + 2 * pd;
+  if (rows > kOuterMaxTd * kOuterSlots) { set_error("space degree too large for the matvec"); return STLS_EINVAL; }
+  // time chunks: enough workgroups to cover the chip, each chunk >= 4 PT slices
+  int nchunk = 1;
+  while (nlb * ntd * nchunk < 1024 && (nt + nchunk) / (nchunk + 1) >= std::max(4 * Dt.p, 8)) ++nchunk;
+  const int Tc = (nt + nchunk - 1) / nchunk;
+  nchunk = (nt + Tc - 1) / Tc;
+  const int blocks = nlb * ntd * nchunk;
+  if (dot_with && blocks > kPartialsCap) { set_error("too many partial sums"); return STLS_EINVAL; }
+  if (nparts) *nparts = blocks;
+  const bool pd_static = (pd == Dt.p);
+  const size_t shmem = sizeof(double) * ((pd_static ? 0 : 3 * (size_t)nd * (2 * pd + 1)) +
+                                         3 * (B ? 3 : 1) * (size_t)rows * kOuterLds);
+  const double k2 = h->kappa * h->kappa, kw = h->kappa * h->dir[d].wend;
+  void (*kern)(const double*, const double*, const double*, double*, int, int, int, int, int, int, int, int, int,
+               const double*, const double*, const double*, const double*, const double*, double, double,
+               const double*, double*) = nullptr;
+  const bool three = B != nullptr, dot = dot_with != nullptr;
+#define STLS_OUTER_VAR(PV, PDV)                                                                  \
+  kern = three ? (dot ? mv_outer_kernel<PV, PDV, true, true> : mv_outer_kernel<PV, PDV, true, false>) \
+               : (dot ? mv_outer_kernel<PV, PDV, false, true> : mv_outer_kernel<PV, PDV, false, false>);
+#define STLS_OUTER_PICK(PV)                                   \
+  case PV:                                                    \
+    if (pd_static) { STLS_OUTER_VAR(PV, PV) } else { STLS_OUTER_VAR(PV, 0) } \
+    break;
+  switch (Dt.p) {
+    STLS_OUTER_PICK(1) STLS_OUTER_PICK(2) STLS_OUTER_PICK(3) STLS_OUTER_PICK(4) STLS_OUTER_PICK(5) STLS_OUTER_PICK(6)
+    default: set_error("time degree > 6 not supported by the matvec kernel"); return STLS_EINVAL;
   }
-  // time mode: y = K_t S1 + M_t S2 (+ S3 on the last slice)
-  {
-    BandProg P{};
-    P.in[0] = S1; P.in[1] = S2;
-    P.nin = 2;
-    P.band[0] = Dt.K; P.band[1] = Dt.M;
-    P.nout = 1;
-    P.out[0] = y;
-    P.nterm[0] = 2; P.term[0][0] = {0, 0, 1.0}; P.term[0][1] = {1, 1, 1.0};
-    P.last_add = S3;
-    P.dotv = dot_with;
-    P.partials = partials;
-    if ((st = launch_band(h, P, (int)h->ns, nt, N, Dt.p, PROF_MV_TIME, nparts))) return st;
-  }
+#undef STLS_OUTER_VAR
+#undef STLS_OUTER_PICK
+  prof_begin(h);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), shmem, h->stream, A, B, C, y, L, nd, nt, pd, Td, nlb, ntd,
+                     nchunk, Tc, Dd.M, Dd.J, Dd.K, Dt.K, Dt.M, k2, kw, dot_with, partials);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "mv_outer_kernel launch");
+  prof_end(h, PROF_MV_OUTER);
   return STLS_OK;
 }
 
