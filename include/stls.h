@@ -139,6 +139,47 @@ int stls_pcg_solve(stls_handle h, const double* b, double* x, double rtol, int m
  * k = 0..iters (host buffer of at least max entries); *count = iters + 1. */
 int stls_pcg_history(stls_handle h, double* out, int max, int* count);
 
+/* ------------------------------------------------------------------------
+ * Differentiation operators (adjoint gradients of a space-time misfit).
+ * Not in the paper; built on its load functional (§3.2) and Kronecker
+ * structure (§4.1).  The forcing f is a spline in the FULL tensor space of
+ * the knot vectors (no boundary or initial restriction): coefficient tensor
+ * of nfull = m_1 * ... * m_d * m_t entries, colexicographic, FP64, device.
+ * kappa is the handle's current diffusivity.  All are stream-ordered and
+ * asynchronous unless they return a host scalar (then they synchronise).
+ * Full-space workspace (two nfull buffers) is allocated on first use.
+ * ------------------------------------------------------------------------ */
+
+/* m[0..d] receives the full sizes m_k (#knots - p - 1), *nfull their product. */
+int stls_get_forcing_shape(stls_handle h, int* m, int64_t* nfull);
+
+/* F = B_kappa f with F_i = int int f (d_t B_i - kappa Lap B_i) (the least-
+ * squares load of §3.2 for the forcing spline f):
+ * B_kappa = C_t (x) Mbar_s - kappa Mbar_t (x) Dbar_s, Mbar = int b_i bbar_j,
+ * C = int b'_i bbar_j, Dbar_s = sum_k (int b''_i bbar_j in direction k,
+ * Mbar elsewhere).  f: nfull doubles; F: ndof doubles. */
+int stls_load_apply(stls_handle h, const double* f, double* F);
+
+/* gf = B_kappa^T l: l ndof doubles, gf nfull doubles. */
+int stls_load_apply_T(stls_handle h, const double* l, double* gf);
+
+/* y = (M_t (x) M_s) x, the Gram matrix of L2(space x time) on the discrete
+ * space (x, y: ndof doubles, must differ). */
+int stls_mass_apply(stls_handle h, const double* x, double* y);
+
+/* *dk (host) = l^T (-(Mbar_t (x) Dbar_s) f - (2 kappa M_t (x) J_s + W_t (x) L_s) u):
+ * the derivative of l^T (F_kappa - A_kappa u) with respect to kappa.
+ * f: nfull doubles; u, l: ndof doubles.  Synchronises. */
+int stls_dkappa(stls_handle h, const double* f, const double* u, const double* l, double* dk);
+
+/* *out (host) = a . b over n doubles (device), fixed-order reduction.
+ * Synchronises. */
+int stls_dot(stls_handle h, const double* a, const double* b, int64_t n, double* out);
+
+/* e = u - ustar, q = (M_t (x) M_s) e (device, ndof), *loss (host) = e . q
+ * (squared L2 norm of u_h - u*_h over the space-time cylinder).  Synchronises. */
+int stls_misfit(stls_handle h, const double* u, const double* ustar, double* q, double* loss);
+
 /* Per-kernel timing with HIP events on the handle's stream (0 = off). */
 int stls_set_profiling(stls_handle h, int on);
 /* Kernel class names and accumulated (launches, milliseconds) since the last

@@ -33,7 +33,7 @@ import torch  # noqa: E402,F401
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libstls.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"{LIB_PATH} is missing: build it with `python -m paper_1809_10026_amd.build` "
+        f"{LIB_PATH} is missing: build it with `python paper_1809_10026_amd/build.py` "
         "(there is no CPU fallback)")
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -61,6 +61,13 @@ _sig = {
     "stls_profile_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     "stls_profile_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "stls_get_forcing_shape": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, ctypes.POINTER(ctypes.c_int64)]),
+    "stls_load_apply": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
+    "stls_load_apply_T": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
+    "stls_mass_apply": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
+    "stls_dkappa": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_dbl_p, ctypes.POINTER(ctypes.c_double)]),
+    "stls_dot": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
+    "stls_misfit": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_dbl_p, ctypes.POINTER(ctypes.c_double)]),
     "stls_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "stls_last_error": (ctypes.c_char_p, []),
 }
@@ -166,6 +173,46 @@ def stls_pcg_history(h):
     return out
 
 
+def stls_get_forcing_shape(h, d):
+    m = (ctypes.c_int * (d + 1))()
+    nf = ctypes.c_int64()
+    _check(_lib.stls_get_forcing_shape(h, m, ctypes.byref(nf)), "stls_get_forcing_shape")
+    return tuple(m), int(nf.value)
+
+
+def stls_load_apply(h, nfull, ndof, f, F):
+    _check(_lib.stls_load_apply(h, _dev_ptr(f, nfull, "f"), _dev_ptr(F, ndof, "F")), "stls_load_apply")
+
+
+def stls_load_apply_T(h, nfull, ndof, lam, gf):
+    _check(_lib.stls_load_apply_T(h, _dev_ptr(lam, ndof, "l"), _dev_ptr(gf, nfull, "gf")), "stls_load_apply_T")
+
+
+def stls_mass_apply(h, ndof, x, y):
+    _check(_lib.stls_mass_apply(h, _dev_ptr(x, ndof, "x"), _dev_ptr(y, ndof, "y")), "stls_mass_apply")
+
+
+def stls_dkappa(h, nfull, ndof, f, u, lam):
+    out = ctypes.c_double()
+    _check(_lib.stls_dkappa(h, _dev_ptr(f, nfull, "f"), _dev_ptr(u, ndof, "u"), _dev_ptr(lam, ndof, "l"),
+                            ctypes.byref(out)), "stls_dkappa")
+    return float(out.value)
+
+
+def stls_dot(h, a, b):
+    out = ctypes.c_double()
+    n = a.numel()
+    _check(_lib.stls_dot(h, _dev_ptr(a, n, "a"), _dev_ptr(b, n, "b"), n, ctypes.byref(out)), "stls_dot")
+    return float(out.value)
+
+
+def stls_misfit(h, ndof, u, ustar, q):
+    out = ctypes.c_double()
+    _check(_lib.stls_misfit(h, _dev_ptr(u, ndof, "u"), _dev_ptr(ustar, ndof, "ustar"), _dev_ptr(q, ndof, "q"),
+                            ctypes.byref(out)), "stls_misfit")
+    return float(out.value)
+
+
 def stls_set_profiling(h, on):
     _check(_lib.stls_set_profiling(h, 1 if on else 0), "stls_set_profiling")
 
@@ -252,6 +299,39 @@ class Solver:
 
     def history(self):
         return stls_pcg_history(self._h)
+
+    # --- differentiation operators ---------------------------------------
+    @property
+    def forcing_shape(self):
+        return stls_get_forcing_shape(self._h, self.d)
+
+    def load_apply(self, f, out=None):
+        import torch
+        F = self._empty() if out is None else out
+        stls_load_apply(self._h, self.forcing_shape[1], self.ndof, f, F)
+        return F
+
+    def load_apply_T(self, lam, out=None):
+        import torch
+        nf = self.forcing_shape[1]
+        gf = torch.empty(nf, dtype=torch.float64, device="cuda") if out is None else out
+        stls_load_apply_T(self._h, nf, self.ndof, lam, gf)
+        return gf
+
+    def mass_apply(self, x, out=None):
+        y = self._empty() if out is None else out
+        stls_mass_apply(self._h, self.ndof, x, y)
+        return y
+
+    def dkappa(self, f, u, lam):
+        return stls_dkappa(self._h, self.forcing_shape[1], self.ndof, f, u, lam)
+
+    def dot(self, a, b):
+        return stls_dot(self._h, a, b)
+
+    def misfit(self, u, ustar):
+        q = self._empty()
+        return stls_misfit(self._h, self.ndof, u, ustar, q), q
 
     def profiling(self, on=True):
         stls_set_profiling(self._h, on)

@@ -1,6 +1,6 @@
 """Build the stls shared library for gfx950 in-tree (hipcc, no JIT cache).
 
-    python -m paper_1809_10026_amd.build
+    python paper_1809_10026_amd/build.py
 
 The library lands next to this file as ``libstls.so``; the Python binding
 loads it from there.  Always recompiles.
@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstls.so")
-SOURCES = ["stls_host.cpp", "stls_kernels.hip"]
+SOURCES = ["stls_host.cpp", "stls_kernels.hip", "stls_diff.hip"]
 
 # Packed FP32 instructions are kept off on purpose: the compiler would emit
 # them from ordinary float code otherwise.
@@ -31,21 +31,28 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    """Compile every translation unit in parallel, then link libstls.so."""
     tmp = LIB + ".tmp"
+    jobs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, src.rsplit(".", 1)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmd = [hipcc(), *HIP_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        errs = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip())
-        if r.returncode != 0:
-            raise RuntimeError(f"compiling {src} failed:\n{errs}")
-        if verbose and errs:
+        jobs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+    objs = []
+    failed = []
+    for src, obj, proc in jobs:
+        _, err = proc.communicate()
+        errs = "\n".join(l for l in err.splitlines() if "packed-fp32-ops" not in l and l.strip())
+        if proc.returncode != 0:
+            failed.append(f"compiling {src} failed:\n{errs}")
+        elif verbose and errs:
             print(errs)
         objs.append(obj)
+    if failed:
+        raise RuntimeError("\n".join(failed))
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -1,0 +1,271 @@
+// Differentiation operators of the stls library (gfx950): load operator of a
+// forcing in the full spline space and its transpose, space-time mass matrix,
+// derivative of the load and of the system matrix with respect to kappa, and
+// deterministic dot products.  They serve the adjoint gradient of the misfit
+// L = (u - u*)^T M_Q (u - u*), u = A_kappa^{-1} B_kappa f:
+//   B_kappa = C_t (x) Mbar_s - kappa Mbar_t (x) Dbar_s   (load F_i = int int f (d_t B_i - kappa Lap B_i), §3.2)
+//   dL/df = B_kappa^T lambda,  lambda = A_kappa^{-1} (2 M_Q e)
+//   dL/dkappa = lambda^T (-(Mbar_t (x) Dbar_s) f - (2 kappa M_t (x) J_s + W_t (x) L_s) u)
+// Every operator is a sum of Kronecker products of banded univariate factors
+// (square restricted factors, or restricted x full rectangular ones), applied
+// mode by mode (eq. kron_vec_multi).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "stls_internal.h"
+
+namespace stls {
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int kMaxBlocks = 8192;
+
+// One banded mode product over the (L, n_in, R) view:
+//   not transposed: out(l, i, r) (+)= coef sum_j B(i, j) in(l, j, r)
+//   transposed:     out(l, i, r) (+)= coef sum_q B(q, i) in(l, q, r)
+// B stored n_rows x (2p+1) with entry (q, j) at q*(2p+1) + (j - q - off + p);
+// off = 0 for the square restricted factors, 1 for restricted x full ones.
+__global__ __launch_bounds__(kT) void band_rect_kernel(const double* __restrict__ in, double* __restrict__ out, int L,
+                                                       int n_in, int n_out, int R, const double* __restrict__ band,
+                                                       int p, int off, int trans, double coef, int accumulate) {
+  const int bw = 2 * p + 1;
+  const long long total = (long long)L * n_out * R;
+  for (long long e = (long long)blockIdx.x * kT + threadIdx.x; e < total; e += (long long)gridDim.x * kT) {
+    const int l = (int)(e % L);
+    const long long rest = e / L;
+    const int i = (int)(rest % n_out);
+    const int r = (int)(rest / n_out);
+    const size_t base = (size_t)l + (size_t)r * L * n_in;
+    double s = 0.0;
+    if (!trans) {
+      const int jlo = max(0, i + off - p), jhi = min(n_in - 1, i + off + p);
+      for (int j = jlo; j <= jhi; ++j) s += band[(size_t)i * bw + (j - i - off + p)] * in[base + (size_t)j * L];
+    } else {
+      const int qlo = max(0, i - off - p), qhi = min(n_in - 1, i - off + p);
+      for (int q = qlo; q <= qhi; ++q) s += band[(size_t)q * bw + (i - q - off + p)] * in[base + (size_t)q * L];
+    }
+    out[e] = accumulate ? out[e] + coef * s : coef * s;
+  }
+}
+
+__global__ __launch_bounds__(kT) void sub_kernel(const double* __restrict__ a, const double* __restrict__ b,
+                                                 double* __restrict__ c, long long n) {
+  for (long long e = (long long)blockIdx.x * kT + threadIdx.x; e < n; e += (long long)gridDim.x * kT) c[e] = a[e] - b[e];
+}
+
+__device__ inline double block_sum_d(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  return s;
+}
+
+__global__ __launch_bounds__(kT) void dot_partial_kernel(const double* __restrict__ a, const double* __restrict__ b,
+                                                         long long n, double* __restrict__ partials) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (long long e = (long long)blockIdx.x * kT + threadIdx.x; e < n; e += (long long)gridDim.x * kT) s += a[e] * b[e];
+  s = block_sum_d(s, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// fixed-order final sum of the partials (deterministic)
+__global__ __launch_bounds__(kT) void dot_final_kernel(const double* __restrict__ partials, int nparts,
+                                                       double* __restrict__ out) {
+  __shared__ double red[4];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kT) v += partials[i];
+  const double s = block_sum_d(v, red);
+  if (threadIdx.x == 0) *out = s;
+}
+
+int grid_for(long long n) { return (int)std::max<long long>(1, std::min<long long>((n + kT - 1) / kT, kMaxBlocks)); }
+
+// One factor of a Kronecker chain.
+struct Fac {
+  const double* band;
+  int p, off, trans, n_in, n_out;
+};
+
+// dst (+)= coef * (F_{d} (x) ... (x) F_0) src on a tensor whose mode sizes are
+// fac[k].n_in; intermediate results ping-pong between t0 and t1.
+int apply_chain(stls_ctx* h, const double* src, double* dst, const std::vector<Fac>& fac, double coef, bool accumulate,
+                double* t0, double* t1) {
+  const int nm = (int)fac.size();
+  std::vector<int> cur(nm);
+  for (int k = 0; k < nm; ++k) cur[k] = fac[k].n_in;
+  const double* in = src;
+  for (int k = 0; k < nm; ++k) {
+    long long L = 1, R = 1;
+    for (int m = 0; m < k; ++m) L *= cur[m];
+    for (int m = k + 1; m < nm; ++m) R *= cur[m];
+    const bool last = k == nm - 1;
+    double* out = last ? dst : (k % 2 == 0 ? t0 : t1);
+    const long long total = L * fac[k].n_out * R;
+    prof_begin(h);
+    hipLaunchKernelGGL(band_rect_kernel, dim3(grid_for(total)), dim3(kT), 0, h->stream, in, out, (int)L, fac[k].n_in,
+                       fac[k].n_out, (int)R, fac[k].band, fac[k].p, fac[k].off, fac[k].trans, last ? coef : 1.0,
+                       (last && accumulate) ? 1 : 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "band_rect_kernel launch");
+    prof_end(h, PROF_DIFF);
+    cur[k] = fac[k].n_out;
+    in = out;
+  }
+  return STLS_OK;
+}
+
+int device_dot(stls_ctx* h, const double* a, const double* b, long long n, double* host_out) {
+  const int nb = std::min(grid_for(n), kPartialsCap);
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(nb), dim3(kT), 0, h->stream, a, b, n, h->partials);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kT), 0, h->stream, h->partials, nb, h->dres);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "dot kernel launch");
+  e = hipMemcpyAsync(h->scal_host, h->dres, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  *host_out = *reinterpret_cast<double*>(h->scal_host);
+  return STLS_OK;
+}
+
+Fac sq(const DevDir& D, const double* band) { return Fac{band, D.p, 0, 0, D.n, D.n}; }
+Fac rect(const DevDir& D, const double* band) { return Fac{band, D.p, 1, 0, D.m, D.n}; }
+Fac rectT(const DevDir& D, const double* band) { return Fac{band, D.p, 1, 1, D.n, D.m}; }
+
+// terms of B_kappa: (coef, factors per mode, time last)
+std::vector<std::pair<double, std::vector<Fac>>> load_terms(stls_ctx* h, bool transpose) {
+  const int d = h->d;
+  auto R = [&](int k, const double* b) { return transpose ? rectT(h->dd[k], b) : rect(h->dd[k], b); };
+  std::vector<std::pair<double, std::vector<Fac>>> terms;
+  std::vector<Fac> f0;
+  for (int k = 0; k < d; ++k) f0.push_back(R(k, h->dd[k].Mbar));
+  f0.push_back(R(d, h->dd[d].Cbar));
+  terms.push_back({1.0, f0});
+  for (int k = 0; k < d; ++k) {
+    std::vector<Fac> f;
+    for (int m = 0; m < d; ++m) f.push_back(R(m, m == k ? h->dd[m].Gbar : h->dd[m].Mbar));
+    f.push_back(R(d, h->dd[d].Mbar));
+    terms.push_back({-h->kappa, f});
+  }
+  return terms;
+}
+
+}  // namespace
+
+}  // namespace stls
+
+using namespace stls;
+
+extern "C" {
+
+int stls_get_forcing_shape(stls_handle h, int* m, int64_t* nfull) {
+  if (!h) { set_error("NULL handle"); return STLS_EINVAL; }
+  int64_t t = 1;
+  for (int k = 0; k <= h->d; ++k) {
+    if (m) m[k] = h->dir[k].m;
+    t *= h->dir[k].m;
+  }
+  if (nfull) *nfull = t;
+  return STLS_OK;
+}
+
+int stls_load_apply(stls_handle h, const double* f, double* F) {
+  if (!h || !f || !F) { set_error("bad handle or pointers"); return STLS_EINVAL; }
+  int st = ensure_diff_operands(h);
+  if (st) return st;
+  bool first = true;
+  for (auto& t : load_terms(h, false)) {
+    if ((st = apply_chain(h, f, F, t.second, t.first, !first, h->ftmp[0], h->ftmp[1]))) return st;
+    first = false;
+  }
+  return STLS_OK;
+}
+
+int stls_load_apply_T(stls_handle h, const double* lam, double* gf) {
+  if (!h || !lam || !gf) { set_error("bad handle or pointers"); return STLS_EINVAL; }
+  int st = ensure_diff_operands(h);
+  if (st) return st;
+  bool first = true;
+  for (auto& t : load_terms(h, true)) {
+    if ((st = apply_chain(h, lam, gf, t.second, t.first, !first, h->ftmp[0], h->ftmp[1]))) return st;
+    first = false;
+  }
+  return STLS_OK;
+}
+
+int stls_mass_apply(stls_handle h, const double* x, double* y) {
+  if (!h || !x || !y || x == y) { set_error("bad handle or pointers (x and y must differ)"); return STLS_EINVAL; }
+  int st = ensure_diff_operands(h);
+  if (st) return st;
+  std::vector<Fac> f;
+  for (int k = 0; k <= h->d; ++k) f.push_back(sq(h->dd[k], h->dd[k].M));
+  return apply_chain(h, x, y, f, 1.0, false, h->ftmp[0], h->ftmp[1]);
+}
+
+int stls_dot(stls_handle h, const double* a, const double* b, int64_t n, double* out) {
+  if (!h || !a || !b || !out || n < 0) { set_error("bad handle or pointers"); return STLS_EINVAL; }
+  return device_dot(h, a, b, n, out);
+}
+
+int stls_dkappa(stls_handle h, const double* f, const double* u, const double* lam, double* dk) {
+  if (!h || !f || !u || !lam || !dk) { set_error("bad handle or pointers"); return STLS_EINVAL; }
+  int st = ensure_diff_operands(h);
+  if (st) return st;
+  const int d = h->d;
+  double* V = h->fdbuf[0];
+  bool first = true;
+  // -(Mbar_t x Dbar_s) f
+  for (int k = 0; k < d; ++k) {
+    std::vector<Fac> fac;
+    for (int m = 0; m < d; ++m) fac.push_back(rect(h->dd[m], m == k ? h->dd[m].Gbar : h->dd[m].Mbar));
+    fac.push_back(rect(h->dd[d], h->dd[d].Mbar));
+    if ((st = apply_chain(h, f, V, fac, -1.0, !first, h->ftmp[0], h->ftmp[1]))) return st;
+    first = false;
+  }
+  // -2 kappa (M_t x J_s) u with J_s = sum_k (J_k) + 2 sum_{k<l} (K_k K_l)
+  const double c2 = -2.0 * h->kappa;
+  for (int k = 0; k < d; ++k) {
+    std::vector<Fac> fac;
+    for (int m = 0; m < d; ++m) fac.push_back(sq(h->dd[m], m == k ? h->dd[m].J : h->dd[m].M));
+    fac.push_back(sq(h->dd[d], h->dd[d].M));
+    if ((st = apply_chain(h, u, V, fac, c2, true, h->ftmp[0], h->ftmp[1]))) return st;
+    for (int l = k + 1; l < d; ++l) {
+      std::vector<Fac> g;
+      for (int m = 0; m < d; ++m) g.push_back(sq(h->dd[m], (m == k || m == l) ? h->dd[m].K : h->dd[m].M));
+      g.push_back(sq(h->dd[d], h->dd[d].M));
+      if ((st = apply_chain(h, u, V, g, 2.0 * c2, true, h->ftmp[0], h->ftmp[1]))) return st;
+    }
+  }
+  // -(W_t x L_s) u: only the final time slice, W_t = w e_T e_T^T
+  const size_t last = (size_t)(h->dir[d].n - 1) * h->ns;
+  const double w = h->dir[d].wend;
+  for (int k = 0; k < d; ++k) {
+    std::vector<Fac> fac;
+    for (int m = 0; m < d; ++m) fac.push_back(sq(h->dd[m], m == k ? h->dd[m].K : h->dd[m].M));
+    if ((st = apply_chain(h, u + last, V + last, fac, -w, true, h->ftmp[0], h->ftmp[1]))) return st;
+  }
+  return device_dot(h, lam, V, h->ndof, dk);
+}
+
+int stls_misfit(stls_handle h, const double* u, const double* ustar, double* q, double* loss) {
+  if (!h || !u || !ustar || !q || !loss) { set_error("bad handle or pointers"); return STLS_EINVAL; }
+  int st = ensure_diff_operands(h);
+  if (st) return st;
+  double* e = h->fdbuf[1];
+  hipLaunchKernelGGL(sub_kernel, dim3(grid_for(h->ndof)), dim3(kT), 0, h->stream, u, ustar, e, (long long)h->ndof);
+  hipError_t er = hipGetLastError();
+  if (er != hipSuccess) return hip_fail(er, "sub_kernel launch");
+  if ((st = stls_mass_apply(h, e, q))) return st;
+  return device_dot(h, e, q, h->ndof, loss);
+}
+
+}  // extern "C"

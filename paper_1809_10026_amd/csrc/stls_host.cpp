@@ -155,6 +155,7 @@ int validate_and_build_dir(const double* knots, int nknots, int p, bool is_time,
   // exact for the piecewise polynomial integrands of degree <= 2p)
   const int bw = 2 * p + 1;
   std::vector<double> Mf((size_t)m * bw, 0.0), Kf((size_t)m * bw, 0.0), Jf((size_t)m * bw, 0.0);
+  std::vector<double> D1f((size_t)m * bw, 0.0), G2f((size_t)m * bw, 0.0);  // int b'_i b_j, int b''_i b_j
   std::vector<double> gx, gw;
   gauss_legendre(p + 1, gx, gw);
   for (int s = p; s < m; ++s) {
@@ -173,6 +174,8 @@ int validate_and_build_dir(const double* knots, int nknots, int p, bool is_time,
           Mf[e] += wq * v[0][r] * v[0][c];
           Kf[e] += wq * v[1][r] * v[1][c];
           Jf[e] += wq * v[2][r] * v[2][c];
+          D1f[e] += wq * v[1][r] * v[0][c];
+          G2f[e] += wq * v[2][r] * v[0][c];
         }
       }
     }
@@ -192,6 +195,19 @@ int validate_and_build_dir(const double* knots, int nknots, int p, bool is_time,
       if (!is_time) out.J[(size_t)ri * bw + o] = Jf[src];
     }
   }
+  // rectangular restricted x full bands: restricted row ri is full row ri + 1
+  out.Mbar.assign((size_t)n * bw, 0.0);
+  out.Cbar.assign((size_t)n * bw, 0.0);
+  out.Gbar.assign((size_t)n * bw, 0.0);
+  for (int ri = 0; ri < n; ++ri)
+    for (int o = 0; o < bw; ++o) {
+      const int j = ri + 1 + o - p;
+      if (j < 0 || j >= m) continue;
+      const size_t src = (size_t)(ri + 1) * bw + o;
+      out.Mbar[(size_t)ri * bw + o] = Mf[src];
+      out.Cbar[(size_t)ri * bw + o] = D1f[src];
+      out.Gbar[(size_t)ri * bw + o] = G2f[src];
+    }
   if (is_time) {
     out.J.clear();
     // W_t = b(1) b(1)^T: evaluate the last non-empty span at its right end
@@ -415,17 +431,40 @@ static int upload_lambda_s(stls_ctx* h) {
   return STLS_OK;
 }
 
+int ensure_diff_operands(stls_ctx* h) {
+  if (h->diff_ready) return STLS_OK;
+  int st = STLS_OK;
+  h->nfull = 1;
+  for (int k = 0; k <= h->d && !st; ++k) {
+    Dir& D = h->dir[k];
+    DevDir& dd = h->dd[k];
+    dd.m = D.m;
+    h->nfull *= D.m;
+    st = dev_upload(&dd.Mbar, D.Mbar.data(), D.Mbar.size(), h->stream);
+    if (!st) st = dev_upload(&dd.Cbar, D.Cbar.data(), D.Cbar.size(), h->stream);
+    if (!st) st = dev_upload(&dd.Gbar, D.Gbar.data(), D.Gbar.size(), h->stream);
+  }
+  if (!st && h->nfull > 2147483647LL) { set_error("forcing space too large"); st = STLS_EINVAL; }
+  for (int i = 0; i < 2 && !st; ++i) {
+    hipError_t e = hipMalloc((void**)&h->ftmp[i], sizeof(double) * (size_t)h->nfull);
+    if (e != hipSuccess) { set_error("hipMalloc forcing workspace"); st = STLS_ENOMEM; }
+  }
+  if (!st) h->diff_ready = true;
+  return st;
+}
+
 static void free_ctx(stls_ctx* h) {
   if (!h) return;
   for (int k = 0; k <= kMaxDim; ++k) {
     DevDir& dd = h->dd[k];
     void* ptrs[] = {dd.M, dd.K, dd.J, dd.Afwd64, dd.Abwd64, dd.Afwd32, dd.Abwd32, dd.Hfwd, dd.Lfwd,
-                    dd.Hbwd, dd.Lbwd, dd.lam};
+                    dd.Hbwd, dd.Lbwd, dd.lam, dd.Mbar, dd.Cbar, dd.Gbar};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
   }
   void* ptrs[] = {h->lam_s, h->lam_s_raw, h->work[0], h->work[1], h->work[2], h->work[3], h->work[4],
-                  h->work[5], h->fdbuf[0], h->fdbuf[1], h->r, h->z, h->pvec, h->q, h->partials, h->scal};
+                  h->work[5], h->fdbuf[0], h->fdbuf[1], h->r, h->z, h->pvec, h->q, h->partials, h->scal,
+                  h->dres, h->ftmp[0], h->ftmp[1]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->scal_host) (void)hipHostFree(h->scal_host);
@@ -538,6 +577,7 @@ int stls_setup(int d, const int* nknots, const double* const* knots, const int* 
   alloc(&h->pvec, nb);
   alloc(&h->q, nb);
   alloc(&h->partials, kPartialsCap * sizeof(double));
+  alloc(&h->dres, 8 * sizeof(double));
   if (!st && hipMalloc((void**)&h->scal, sizeof(PcgScalars)) != hipSuccess) { set_error("hipMalloc"); st = STLS_ENOMEM; }
   if (!st && hipHostMalloc((void**)&h->scal_host, sizeof(PcgScalars), hipHostMallocDefault) != hipSuccess) {
     set_error("hipHostMalloc");
@@ -614,7 +654,7 @@ int stls_pcg_history(stls_handle h, double* out, int max, int* count) {
 }
 
 static const char* kProfNames[PROF_COUNT] = {"fd_space", "fd_time", "mv_inner1", "mv_inner2", "mv_outer",
-                                             "vec", "reduce"};
+                                             "vec", "reduce", "diff"};
 
 int stls_set_profiling(stls_handle h, int on) {
   if (!h) { set_error("NULL handle"); return STLS_EINVAL; }

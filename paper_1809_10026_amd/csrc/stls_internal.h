@@ -24,6 +24,9 @@ struct Dir {
   std::vector<double> knots;
   // banded restricted matrices, n x (2p+1), entry (i,j) at i*(2p+1)+(j-i+p)
   std::vector<double> M, K, J;
+  // restricted x full rectangular bands (forcing in the full space), n x (2p+1):
+  // entry (i, j) with j the full index at i*(2p+1) + (j - (i+1) + p)
+  std::vector<double> Mbar, Cbar, Gbar;  // int b_i bbar_j, int b'_i bbar_j, int b''_i bbar_j
   std::vector<double> U;    // n x n column-major, U^T M U = I
   std::vector<double> lam;  // generalized eigenvalues
   double wend = 0.0;        // b_{m}(1)^2 (time): the single entry of W_t
@@ -45,6 +48,10 @@ struct DevDir {
   uint16_t* Lbwd = nullptr;
   int kpad = 0;
   double* lam = nullptr;
+  int m = 0;                   // full space size (forcing coefficients)
+  double* Mbar = nullptr;      // rectangular bands (uploaded on first use)
+  double* Cbar = nullptr;
+  double* Gbar = nullptr;
 };
 
 // Scalars of the PCG recurrence, resident in device memory.
@@ -68,6 +75,7 @@ enum ProfId {
   PROF_MV_OUTER,      // matvec outer stage (last space direction and time)
   PROF_VEC,           // PCG vector kernels
   PROF_REDUCE,        // PCG scalar finalisation kernels
+  PROF_DIFF,          // differentiation operators (load, transpose, mass, d/dkappa)
   PROF_COUNT
 };
 
@@ -93,6 +101,10 @@ struct stls_ctx {
   double* pvec = nullptr;
   double* q = nullptr;
   double* partials = nullptr;
+  double* dres = nullptr;          // device scalar result of stls_dot
+  double* ftmp[2] = {nullptr, nullptr};  // full-space temporaries (differentiation ops)
+  int64_t nfull = 0;               // prod of full sizes m_k
+  bool diff_ready = false;
   stls::PcgScalars* scal = nullptr;
   stls::PcgScalars* scal_host = nullptr;  // pinned
   std::vector<double> history;
@@ -127,6 +139,7 @@ int launch_matvec(stls_ctx* h, const double* x, double* y, const double* dot_wit
 int pcg_run(stls_ctx* h, const double* b, double* x, double rtol, int maxit, int* iters,
             double* relres);
 int upload_fd_operands(stls_ctx* h, int k);
+int ensure_diff_operands(stls_ctx* h);
 
 // profiling helpers
 void prof_begin(stls_ctx* h);

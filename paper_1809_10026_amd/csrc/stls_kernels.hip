@@ -326,6 +326,277 @@ static int launch_fd_mode(stls_ctx* h, const TI* X, TO* Y, int L, int n, int nco
   return STLS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// BF16x3 mode product.  Operands are FP32; each is split into bf16 hi + lo
+// (hi = bf16(x), lo = bf16(x - hi)) and the product is formed as
+// W_hi X_hi + W_hi X_lo + W_lo X_hi on MFMA bf16 16x16x32 with FP32
+// accumulation (the lo*lo term, relative size 2^-18, is dropped).
+// Fragment layout (16x16x32): lane l supplies A(i = l%16, k = 8(l/16)+e) and
+// B(k = 8(l/16)+e, j = l%16), e = 0..7; results as for f32 16x16x4.
+// The panel is staged as hi/lo halves in [column][k] order (8 consecutive k
+// per 16-byte read); W halves are row-major [i][k].  Same orientation, fused
+// time and dot conventions as fd_mode_kernel.
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short us8_t __attribute__((ext_vector_type(8)));
+
+__device__ inline unsigned short bf16_rne(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_to_float(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+template <typename TI, typename TO, int NM, bool TRANS, bool FUSED, bool DOT>
+__global__ __launch_bounds__(kThreads) void fd_mode_bf16x3_kernel(
+    const TI* __restrict__ X, TO* __restrict__ Y, int L, int n, int ncols, const unsigned short* __restrict__ Wh,
+    const unsigned short* __restrict__ Wl, const unsigned short* __restrict__ W2h,
+    const unsigned short* __restrict__ W2l, const double* __restrict__ lam_t, const double* __restrict__ lam_s,
+    const double* __restrict__ dotv, double* __restrict__ partials) {
+  constexpr int NPAD = NM * 16;
+  constexpr int NK = (NM + 1) / 2;  // 32-wide k steps
+  constexpr int KPAD = NK * 32;
+  constexpr int LDK = KPAD + 8;     // bf16 row stride: 16-byte fragment reads hit distinct banks
+  constexpr int PER = NPAD * kCols / kThreads;
+  constexpr int NW = FUSED ? 2 : 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned short* Ws = reinterpret_cast<unsigned short*>(smem_raw);  // NW x {hi, lo} x NPAD x LDK
+  unsigned short* Xh = Ws + NW * 2 * NPAD * LDK;                     // kCols x LDK
+  unsigned short* Xl = Xh + kCols * LDK;
+  double* red = reinterpret_cast<double*>(Xl + kCols * LDK);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int npanels = (ncols + kCols - 1) / kCols;
+  const int ccol = wave * 16 + (lane & 15);
+  double dsum = 0.0;
+
+  auto stage_w = [&](const unsigned short* __restrict__ h, const unsigned short* __restrict__ l, int slot) {
+    unsigned short* dh = Ws + slot * 2 * NPAD * LDK;
+    unsigned short* dl = dh + NPAD * LDK;
+    for (int e = tid; e < NPAD * KPAD; e += kThreads) {
+      const int i = e / KPAD, kk = e - i * KPAD;
+      dh[i * LDK + kk] = h[e];
+      dl[i * LDK + kk] = l[e];
+    }
+  };
+  stage_w(Wh, Wl, 0);
+  if constexpr (FUSED) stage_w(W2h, W2l, 1);
+  double lt[FUSED ? NM * 4 : 1];
+  if constexpr (FUSED) {
+#pragma unroll
+    for (int t = 0; t < NM; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) lt[t * 4 + r] = lam_t[min(t * 16 + 4 * (lane >> 4) + r, n - 1)];
+  }
+  auto column_base = [&](int cc) -> int {
+    if constexpr (TRANS) return cc * n;
+    return (cc % L) + (cc / L) * L * n;
+  };
+  auto put = [&](int j, int c, float v) {
+    const unsigned short hi = bf16_rne(v);
+    Xh[c * LDK + j] = hi;
+    Xl[c * LDK + j] = bf16_rne(v - bf16_to_float(hi));
+  };
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  f4v acc[NM];
+  auto gemm = [&](int slot) {
+    const unsigned short* wh = Ws + slot * 2 * NPAD * LDK;
+    const unsigned short* wl = wh + NPAD * LDK;
+#pragma unroll
+    for (int t = 0; t < NM; ++t) acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < NK; ++kb) {
+      const int koff = kb * 32 + 8 * (lane >> 4);
+      const bf8_t xh = __builtin_bit_cast(bf8_t, *reinterpret_cast<const us8_t*>(Xh + ccol * LDK + koff));
+      const bf8_t xl = __builtin_bit_cast(bf8_t, *reinterpret_cast<const us8_t*>(Xl + ccol * LDK + koff));
+#pragma unroll
+      for (int t = 0; t < NM; ++t) {
+        const int row = (t * 16 + (lane & 15)) * LDK + koff;
+        const bf8_t ah = __builtin_bit_cast(bf8_t, *reinterpret_cast<const us8_t*>(wh + row));
+        const bf8_t al = __builtin_bit_cast(bf8_t, *reinterpret_cast<const us8_t*>(wl + row));
+        if constexpr (TRANS) {
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, ah, acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, ah, acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, al, acc[t], 0, 0, 0);
+        } else {
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xh, acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, xl, acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, xh, acc[t], 0, 0, 0);
+        }
+      }
+    }
+  };
+  auto out_pos = [&](int c0p, int t, int r, int& i, int& cc) {
+    if constexpr (TRANS) { cc = c0p + wave * 16 + 4 * (lane >> 4) + r; i = t * 16 + (lane & 15); }
+    else { cc = c0p + ccol; i = t * 16 + 4 * (lane >> 4) + r; }
+  };
+
+  for (int pn = blockIdx.x; pn < npanels; pn += gridDim.x) {
+    const int c0 = pn * kCols;
+    __syncthreads();  // W staged; previous panel's readers are done
+    // stage the panel (entries with j >= n, including the k padding, are zero)
+    if constexpr (TRANS) {
+#pragma unroll
+      for (int s = 0; s < PER; ++s) {
+        const int e = tid + kThreads * s;
+        const int c = e / NPAD, j = e - c * NPAD;
+        const int cc = c0 + c;
+        const bool ok = cc < ncols && j < n;
+        const TI v = X[ok ? (size_t)cc * n + j : 0];
+        put(j, c, ok ? (float)v : 0.f);
+      }
+    } else {
+      const int c = tid & (kCols - 1);
+      const int cc = c0 + c;
+      const bool okc = cc < ncols;
+      const size_t b = okc ? (size_t)column_base(cc) : 0;
+#pragma unroll
+      for (int s = 0; s < PER; ++s) {
+        const int j = (tid >> 6) + (kThreads / kCols) * s;
+        const bool ok = okc && j < n;
+        const TI v = X[ok ? b + (size_t)j * L : 0];
+        put(j, c, ok ? (float)v : 0.f);
+      }
+    }
+    if constexpr (KPAD > NPAD) {  // k padding beyond NPAD rows
+      for (int e = tid; e < kCols * (KPAD - NPAD); e += kThreads) {
+        const int c = e / (KPAD - NPAD), j = NPAD + e % (KPAD - NPAD);
+        Xh[c * LDK + j] = 0;
+        Xl[c * LDK + j] = 0;
+      }
+    }
+    double ls = 1.0;
+    if constexpr (FUSED) ls = lam_s[min(c0 + ccol, ncols - 1)];
+    double dv[DOT ? NM * 4 : 1];
+    if constexpr (DOT) {
+#pragma unroll
+      for (int t = 0; t < NM; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int i, cc;
+          out_pos(c0, t, r, i, cc);
+          const bool ok = cc < ncols && i < n;
+          const double v = dotv[ok ? (size_t)column_base(cc) + (size_t)i * L : 0];
+          dv[t * 4 + r] = ok ? v : 0.0;
+        }
+    }
+    __syncthreads();
+    gemm(0);
+    if constexpr (FUSED) {
+      __syncthreads();  // all waves are done reading the panel
+#pragma unroll
+      for (int t = 0; t < NM; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = t * 16 + 4 * (lane >> 4) + r;
+          const double v = (double)acc[t][r] / (lt[t * 4 + r] + ls);
+          put(i, ccol, i < n ? (float)v : 0.f);
+        }
+      __syncthreads();
+      gemm(1);
+    }
+#pragma unroll
+    for (int t = 0; t < NM; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int i, cc;
+        out_pos(c0, t, r, i, cc);
+        const TO v = (TO)acc[t][r];
+        if constexpr (DOT) dsum += (double)v * dv[t * 4 + r];
+        if (cc < ncols && i < n) Y[(size_t)column_base(cc) + (size_t)i * L] = v;
+      }
+  }
+  if constexpr (DOT) {
+    const double s = block_sum(dsum, red);
+    if (tid == 0) partials[blockIdx.x] = s;
+  }
+}
+
+template <typename TI, typename TO, bool TRANS, bool FUSED, bool DOT>
+static int launch_fd_bf16(stls_ctx* h, const TI* X, TO* Y, int L, int n, int ncols, int k, bool fwd, int k2,
+                          const double* lam_t, const double* dotv, double* partials, int* nparts) {
+  const DevDir& D = h->dd[k];
+  const int nm = D.npad / 16;
+  const int nk = (nm + 1) / 2, kpad = nk * 32, ldk = kpad + 8;
+  if (kpad != D.kpad) { set_error("bf16 operand padding mismatch"); return STLS_EINVAL; }
+  const int npanels = (ncols + kCols - 1) / kCols;
+  const size_t shmem = sizeof(unsigned short) * ((FUSED ? 2 : 1) * 2 * (size_t)D.npad * ldk + 2 * (size_t)kCols * ldk) +
+                       4 * sizeof(double) + 16;
+  if (shmem > 160 * 1024) { set_error("direction too large for the bf16 FD kernel"); return STLS_EINVAL; }
+  const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / shmem)));
+  const int blocks = std::min(npanels, 256 * per_cu);
+  if (DOT && blocks > kPartialsCap) { set_error("too many partial sums"); return STLS_EINVAL; }
+  if (nparts) *nparts = blocks;
+  const unsigned short* Wh = fwd ? D.Hfwd : D.Hbwd;
+  const unsigned short* Wl = fwd ? D.Lfwd : D.Lbwd;
+  const unsigned short* W2h = FUSED ? h->dd[k2].Hbwd : nullptr;
+  const unsigned short* W2l = FUSED ? h->dd[k2].Lbwd : nullptr;
+  void (*kern)(const TI*, TO*, int, int, int, const unsigned short*, const unsigned short*, const unsigned short*,
+               const unsigned short*, const double*, const double*, const double*, double*) = nullptr;
+#define STLS_BF_PICK(NMV) \
+  case NMV: kern = fd_mode_bf16x3_kernel<TI, TO, NMV, TRANS, FUSED, DOT>; break;
+  switch (nm) {
+    STLS_BF_PICK(1) STLS_BF_PICK(2) STLS_BF_PICK(3) STLS_BF_PICK(4) STLS_BF_PICK(5) STLS_BF_PICK(6)
+    STLS_BF_PICK(7) STLS_BF_PICK(8) STLS_BF_PICK(9) STLS_BF_PICK(10) STLS_BF_PICK(11) STLS_BF_PICK(12)
+    STLS_BF_PICK(13) STLS_BF_PICK(14) STLS_BF_PICK(15) STLS_BF_PICK(16)
+    default: set_error("direction too large for the bf16 FD kernel"); return STLS_EINVAL;
+  }
+#undef STLS_BF_PICK
+  if (shmem > 65536) {
+    hipError_t ea = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (ea != hipSuccess) return hip_fail(ea, "hipFuncSetAttribute(LDS)");
+  }
+  prof_begin(h);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), shmem, h->stream, X, Y, L, n, ncols, Wh, Wl, W2h, W2l, lam_t,
+                     h->lam_s, dotv, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "fd_mode_bf16x3_kernel launch");
+  prof_end(h, FUSED ? PROF_FD_TIME : PROF_FD_SPACE);
+  return STLS_OK;
+}
+
+// BF16x3 chain: FP32 intermediates, bf16 split products.
+static int prec_apply_bf16x3(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
+                             int* nparts) {
+  const int d = h->d;
+  const int nt = h->dir[d].n;
+  const int ns = (int)h->ns;
+  float* buf[2] = {reinterpret_cast<float*>(h->fdbuf[0]), reinterpret_cast<float*>(h->fdbuf[1])};
+  int st, cur = 0, L = 1;
+  for (int k = 0; k < d; ++k) {
+    const int n = h->dir[k].n;
+    const int ncols = (int)(h->ndof / n);
+    if (k == 0) st = launch_fd_bf16<double, float, true, false, false>(h, r, buf[cur], L, n, ncols, k, true, 0, nullptr,
+                                                                      nullptr, nullptr, nullptr);
+    else {
+      st = launch_fd_bf16<float, float, false, false, false>(h, buf[cur], buf[cur ^ 1], L, n, ncols, k, true, 0,
+                                                             nullptr, nullptr, nullptr, nullptr);
+      cur ^= 1;
+    }
+    if (st) return st;
+    L *= n;
+  }
+  st = launch_fd_bf16<float, float, false, true, false>(h, buf[cur], buf[cur ^ 1], ns, nt, ns, d, true, d,
+                                                        h->dd[d].lam, nullptr, nullptr, nullptr);
+  if (st) return st;
+  cur ^= 1;
+  for (int k = d - 1; k >= 0; --k) {
+    const int n = h->dir[k].n;
+    L /= n;
+    const int ncols = (int)(h->ndof / n);
+    if (k == 0)
+      st = dot_with ? launch_fd_bf16<float, double, true, false, true>(h, buf[cur], s, L, n, ncols, k, false, 0,
+                                                                       nullptr, dot_with, partials, nparts)
+                    : launch_fd_bf16<float, double, true, false, false>(h, buf[cur], s, L, n, ncols, k, false, 0,
+                                                                        nullptr, nullptr, nullptr, nparts);
+    else {
+      st = launch_fd_bf16<float, float, false, false, false>(h, buf[cur], buf[cur ^ 1], L, n, ncols, k, false, 0,
+                                                             nullptr, nullptr, nullptr, nullptr);
+      cur ^= 1;
+    }
+    if (st) return st;
+  }
+  return STLS_OK;
+}
+
 // Forward chain over space modes, fused time kernel, backward chain; the
 // last backward product writes s (FP64) and optionally the partial sums of
 // s . dot_with.
@@ -389,6 +660,7 @@ int launch_prec_apply(stls_ctx* h, const double* r, double* s, const double* dot
   switch (h->fd_mode) {
     case STLS_FD_FP64: return prec_apply_t<double>(h, r, s, dot_with, partials, nparts);
     case STLS_FD_FP32: return prec_apply_t<float>(h, r, s, dot_with, partials, nparts);
+    case STLS_FD_BF16X3: return prec_apply_bf16x3(h, r, s, dot_with, partials, nparts);
     default: set_error("FD precision mode not available"); return STLS_EINVAL;
   }
 }

@@ -28,7 +28,7 @@ from tests.gpu_util import rel_err, to_dev, to_host  # noqa: E402
 
 
 def _lib():
-    assert stls is not None, "libstls.so is not built; run python -m paper_1809_10026_amd.build"
+    assert stls is not None, "libstls.so is not built; run python paper_1809_10026_amd/build.py"
     return stls
 
 
@@ -135,6 +135,41 @@ def test_prec_apply_fp32_error_bound(d, nel, p, kappa):
     s_ref = osys.vec(ofd.FD(P).apply(r))
     # 2(d+1) FP32 products of length <= n with well-conditioned U (cond <= ~15)
     assert rel_err(s, s_ref) < 2e-5
+
+
+@pytest.mark.parametrize("d,nel,p,kappa", CASES)
+def test_prec_apply_bf16x3_error_bound(d, nel, p, kappa):
+    """BF16x3 products: each operand split into bf16 hi + lo, three MFMA
+    products with FP32 accumulation; the dropped lo*lo term and the lo
+    rounding are 2^-18 relative, so 2(d+1) products with cond(U) <= ~15
+    stay below 5e-4 relative."""
+    S = _lib().Solver(*problem_knots(d, nel, p), kappa=kappa)
+    P = osys.Problem(*problem_knots(d, nel, p), kappa=kappa)
+    S.set_fd_precision(stls.STLS_FD_BF16X3)
+    r = uniform_pm1(P.ndof, 14)
+    s = to_host(S.prec_apply(to_dev(r)))
+    s_ref = osys.vec(ofd.FD(P).apply(r))
+    assert rel_err(s, s_ref) < 5e-4
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("d,nel,p", [(2, 16, 3), (3, 8, 4)])
+def test_pcg_mixed_precision_reaches_fp64_tolerance(mode, d, nel, p):
+    """Low-precision FD inside the FP64 PCG still reaches rtol = 1e-8 on the
+    true residual; the solution matches the oracle's to the solve tolerance."""
+    knots, degs = problem_knots(d, nel, p)
+    P = osys.Problem(knots, degs)
+    b = uniform_pm1(P.ndof, 21)
+    S = _lib().Solver(knots, degs)
+    S.set_fd_precision(mode)
+    x, it, rel = S.solve(to_dev(b), rtol=1e-8, maxit=300)
+    xo = to_host(x)
+    true_rel = np.linalg.norm(b - osys.vec(P.matvec(xo))) / np.linalg.norm(b)
+    assert rel <= 1e-8 and true_rel < 2e-8
+    fdo = ofd.FD(P)
+    x_ref, info = opcg.pcg(lambda v: osys.vec(P.matvec(v)), lambda v: osys.vec(fdo.apply(v)), b, 1e-8)
+    assert it <= info["iters"] + 6
+    assert rel_err(xo, x_ref) < 2 * d * 10 * 1e-8
 
 
 def _manufactured_rhs(d, knots, degs, kappa=1.0):
