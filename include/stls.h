@@ -180,6 +180,48 @@ int stls_dot(stls_handle h, const double* a, const double* b, int64_t n, double*
  * (squared L2 norm of u_h - u*_h over the space-time cylinder).  Synchronises. */
 int stls_misfit(stls_handle h, const double* u, const double* ustar, double* q, double* loss);
 
+/* ------------------------------------------------------------------------
+ * Batched PCG: many independent problems of uneven sizes and degrees solved
+ * together.  Every PCG step of the whole batch is one kernel launch over a
+ * work list of (problem, tile) items; alpha, beta, rho and the convergence
+ * flag of each problem stay in device memory and converged problems skip
+ * their items.  FD products in FP64.  Supported: d = 1 or 2 (the same for
+ * the whole batch), the same degree (<= 6) in every direction of a problem,
+ * n <= 112 per direction.
+ * ------------------------------------------------------------------------ */
+typedef struct stls_batch_ctx* stls_batch_handle;
+
+/* nprob problems; problem i has knot vectors knots[i*(d+1) + k] (host, copied)
+ * of lengths nknots[i*(d+1) + k], degrees degree[i*(d+1) + k] and diffusivity
+ * kappa[i] (validation as in stls_setup).  Per-problem setup runs in host
+ * threads.  Synchronises.  Errors: STLS_EINVAL (including the problem index
+ * in stls_last_error), STLS_ENOMEM, STLS_EHIP. */
+int stls_batch_setup(int nprob, int d, const int* nknots, const double* const* knots, const int* degree,
+                     const double* kappa, void* stream, stls_batch_handle* out);
+
+/* Release the batch and its problems (NULL is a no-op). */
+int stls_batch_destroy(stls_batch_handle b);
+
+/* Batch vectors are the problems' vectors concatenated: problem i occupies
+ * [off[i], off[i+1]) (host array of nprob + 1 entries). */
+int stls_batch_offsets(stls_batch_handle b, int64_t* off);
+
+/* Handle of problem i (owned by the batch; valid until stls_batch_destroy),
+ * for single-problem calls on the same factors. */
+int stls_batch_problem(stls_batch_handle b, int i, stls_handle* h);
+
+/* Batched y = A x and s = P^{-1} r over concatenated vectors (asynchronous). */
+int stls_batch_matvec(stls_batch_handle b, const double* x, double* y);
+int stls_batch_prec_apply(stls_batch_handle b, const double* r, double* s);
+
+/* Batched PCG from x = 0 to ||r_i||/||b_i|| <= rtol for every problem i.
+ * b, x: device, concatenated.  iters, relres: host arrays of nprob (may be
+ * NULL).  Synchronises once per iteration (all problems' scalars in one copy).
+ * Returns STLS_OK when all converged, STLS_ENOCONV if any hit maxit,
+ * STLS_ENAN / STLS_EBREAKDOWN if any problem failed. */
+int stls_batch_pcg_solve(stls_batch_handle b, const double* bvec, double* x, double rtol, int maxit, int* iters,
+                         double* relres);
+
 /* Per-kernel timing with HIP events on the handle's stream (0 = off). */
 int stls_set_profiling(stls_handle h, int on);
 /* Kernel class names and accumulated (launches, milliseconds) since the last

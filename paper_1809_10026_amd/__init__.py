@@ -68,6 +68,16 @@ _sig = {
     "stls_dkappa": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_dbl_p, ctypes.POINTER(ctypes.c_double)]),
     "stls_dot": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     "stls_misfit": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_dbl_p, ctypes.POINTER(ctypes.c_double)]),
+    "stls_batch_setup": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_int_p, ctypes.POINTER(ctypes.c_void_p), _c_int_p,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "stls_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "stls_batch_offsets": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "stls_batch_problem": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "stls_batch_matvec": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
+    "stls_batch_prec_apply": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
+    "stls_batch_pcg_solve": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, ctypes.c_double, ctypes.c_int,
+                                            _c_int_p, ctypes.POINTER(ctypes.c_double)]),
     "stls_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "stls_last_error": (ctypes.c_char_p, []),
 }
@@ -231,6 +241,83 @@ def stls_profile(h):
 
 def stls_profile_reset(h):
     _check(_lib.stls_profile_reset(h), "stls_profile_reset")
+
+
+# ---------------------------------------------------------------------------
+class Batch:
+    """Many independent problems solved together (one launch per PCG step).
+
+    problems: list of (knots, degrees, kappa) with the same d (1 or 2).
+    Vectors are concatenated float64 CUDA tensors; ``offsets[i]:offsets[i+1]``
+    is problem i.
+    """
+
+    def __init__(self, problems, stream=None):
+        self.nprob = len(problems)
+        self.d = len(problems[0][0]) - 1
+        d1 = self.d + 1
+        arrs, nks, degs, kaps = [], [], [], []
+        for knots, degrees, kappa in problems:
+            if len(knots) != d1:
+                raise ValueError("all problems of a batch need the same d")
+            for k in knots:
+                arrs.append(np.ascontiguousarray(k, dtype=np.float64))
+                nks.append(len(arrs[-1]))
+            degs.extend(int(p) for p in degrees)
+            kaps.append(float(kappa))
+        nk = (ctypes.c_int * len(nks))(*nks)
+        ptrs = (ctypes.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
+        dg = (ctypes.c_int * len(degs))(*degs)
+        kp = (ctypes.c_double * len(kaps))(*kaps)
+        h = ctypes.c_void_p()
+        _check(_lib.stls_batch_setup(self.nprob, self.d, nk, ptrs, dg, kp, _stream_ptr(stream), ctypes.byref(h)),
+               "stls_batch_setup")
+        self._h = h
+        off = (ctypes.c_int64 * (self.nprob + 1))()
+        _check(_lib.stls_batch_offsets(h, off), "stls_batch_offsets")
+        self.offsets = [int(v) for v in off]
+        self.total = self.offsets[-1]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(_lib.stls_batch_destroy(self._h), "stls_batch_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def problem_handle(self, i):
+        h = ctypes.c_void_p()
+        _check(_lib.stls_batch_problem(self._h, i, ctypes.byref(h)), "stls_batch_problem")
+        return h
+
+    def _empty(self):
+        import torch
+        return torch.empty(self.total, dtype=torch.float64, device="cuda")
+
+    def matvec(self, x, out=None):
+        y = self._empty() if out is None else out
+        _check(_lib.stls_batch_matvec(self._h, _dev_ptr(x, self.total, "x"), _dev_ptr(y, self.total, "y")),
+               "stls_batch_matvec")
+        return y
+
+    def prec_apply(self, r, out=None):
+        s = self._empty() if out is None else out
+        _check(_lib.stls_batch_prec_apply(self._h, _dev_ptr(r, self.total, "r"), _dev_ptr(s, self.total, "s")),
+               "stls_batch_prec_apply")
+        return s
+
+    def solve(self, b, rtol=1e-8, maxit=500, out=None, raise_on_noconv=True):
+        x = self._empty() if out is None else out
+        its = (ctypes.c_int * self.nprob)()
+        rel = (ctypes.c_double * self.nprob)()
+        ok = (STLS_OK,) if raise_on_noconv else (STLS_OK, STLS_ENOCONV)
+        _check(_lib.stls_batch_pcg_solve(self._h, _dev_ptr(b, self.total, "b"), _dev_ptr(x, self.total, "x"),
+                                         float(rtol), int(maxit), its, rel), "stls_batch_pcg_solve", ok)
+        return x, list(its), list(rel)
 
 
 # ---------------------------------------------------------------------------

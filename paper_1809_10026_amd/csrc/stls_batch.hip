@@ -1,0 +1,824 @@
+// Batched FD-preconditioned PCG for many independent heat problems of uneven
+// sizes and degrees (gfx950).  Each problem is a regular stls handle (its
+// factors stay where stls_setup put them); the batch concatenates the PCG
+// vectors of all problems and runs every PCG step as ONE launch over a work
+// list of (problem, tile) items, with per-problem scalars alpha, beta, rho,
+// convergence flags and fixed-order segmented reductions in device memory.
+// Problems that have converged skip their items.
+//
+// Operators per problem are those of the single-problem path (FD of §4.3
+// Algorithm 1 in FP64 on MFMA, Kronecker-sum matvec of §4.1 eq. A_kron);
+// supported: d = 1 or 2, the same degree (<= 6) in every direction, n <= 112
+// per direction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "stls_internal.h"
+
+namespace stls {
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int kBCols = 64;            // FD panel width
+constexpr int kBLdx = kBCols + 1;     // panel LDS row stride (static LDS stays below 64 KB)
+constexpr int kBNM = 7;               // max 16-row tiles per direction (n <= 112)
+constexpr int kVecChunk = 4096;       // elements per vector work item
+constexpr int kInChunk = 1024;        // elements per inner-stage work item
+constexpr int kOLb = 16, kOMaxTd = 16, kOSlots = 2;
+
+typedef double d4b_t __attribute__((ext_vector_type(4)));
+
+// Device descriptor of one problem.
+struct BProb {
+  long long off;   // offset of the problem's vectors in the concatenated buffers
+  int N, ns, d, pad0;
+  int n[3], p[3], npad[3];
+  const double* Af[3];
+  const double* Ab[3];
+  const double* M[3];
+  const double* K[3];
+  const double* J[3];
+  const double* lam_t;
+  const double* lam_s;
+  double k2, kw;
+  int Td, nlb, ntd, nchunk, Tc, pad1;
+};
+
+struct Item {
+  int prob, idx;
+};
+
+__device__ inline double bsum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+__device__ inline bool skip(const PcgScalars* S, int prob) { return S[prob].done || S[prob].flag; }
+
+// ---------------------------------------------------------------------------
+// FD mode product over one panel of kBCols columns of one problem; W (n x n,
+// zero padded to npad) read from global memory as W[j*npad + i].  mode: space
+// direction (0..d-1) or d = fused time (forward product, FP64 division by
+// lambda_t[i] + lambda_s[c], backward product).  TRANS: contiguous mode 0.
+template <bool TRANS, bool FUSED, bool DOT>
+__global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, double* __restrict__ Y,
+                                                 const BProb* __restrict__ P, const Item* __restrict__ items,
+                                                 int nitems, int mode, int bwd, const PcgScalars* __restrict__ S,
+                                                 const double* __restrict__ dotv, double* __restrict__ partials) {
+  __shared__ double Xs[kBNM * 16 * kBLdx];
+  __shared__ double red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ccol = wave * 16 + (lane & 15), krow = lane >> 4;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const Item I = items[it];
+    const BProb& B = P[I.prob];
+    if (skip(S, I.prob)) continue;
+    const int n = B.n[mode], npad = B.npad[mode], nm = npad / 16;
+    int L = 1;
+    for (int m = 0; m < mode; ++m) L *= B.n[m];
+    const int ncols = B.N / n;
+    const double* W = FUSED ? B.Af[mode] : (bwd ? B.Ab[mode] : B.Af[mode]);
+    const double* Xp = X + B.off;
+    double* Yp = Y + B.off;
+    const int c0 = I.idx * kBCols;
+    auto base = [&](int cc) -> int { return TRANS ? cc * n : (cc % L) + (cc / L) * L * n; };
+    __syncthreads();
+    for (int e = tid; e < kBCols * npad; e += kT) {
+      int j, c;
+      if (TRANS) { c = e / npad; j = e - c * npad; }
+      else { j = e / kBCols; c = e - j * kBCols; }
+      const int cc = c0 + c;
+      const bool ok = cc < ncols && j < n;
+      const double v = Xp[ok ? (size_t)base(cc) + (size_t)j * L : 0];
+      Xs[j * kBLdx + c] = ok ? v : 0.0;
+    }
+    __syncthreads();
+    d4b_t acc[kBNM];
+    auto gemm = [&](const double* Wm) {
+#pragma unroll
+      for (int t = 0; t < kBNM; ++t) acc[t] = d4b_t{0, 0, 0, 0};
+      for (int k0 = 0; k0 < n; k0 += 4) {
+        const double xv = Xs[(k0 + krow) * kBLdx + ccol];
+#pragma unroll
+        for (int t = 0; t < kBNM; ++t) {
+          if (t < nm) {
+            const double wv = Wm[(size_t)(k0 + krow) * npad + t * 16 + (lane & 15)];
+            if (TRANS) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, wv, acc[t], 0, 0, 0);
+            else acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv, xv, acc[t], 0, 0, 0);
+          }
+        }
+      }
+    };
+    gemm(W);
+    if (FUSED) {
+      const int cc = c0 + ccol;
+      const double ls = B.lam_s[min(cc, ncols - 1)];
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < kBNM; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = t * 16 + (lane >> 4) + 4 * r;
+          if (t < nm) {
+            const double v = acc[t][r] / (B.lam_t[min(i, n - 1)] + ls);
+            Xs[i * kBLdx + ccol] = i < n ? v : 0.0;
+          }
+        }
+      __syncthreads();
+      gemm(B.Ab[mode]);
+    }
+    double ds = 0.0;
+#pragma unroll
+    for (int t = 0; t < kBNM; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (t >= nm) continue;
+        int i, cc;
+        if (TRANS) { cc = c0 + wave * 16 + (lane >> 4) + 4 * r; i = t * 16 + (lane & 15); }
+        else { cc = c0 + ccol; i = t * 16 + (lane >> 4) + 4 * r; }
+        if (cc < ncols && i < n) {
+          const size_t o = (size_t)base(cc) + (size_t)i * L;
+          Yp[o] = acc[t][r];
+          if (DOT) ds += acc[t][r] * dotv[B.off + o];
+        }
+      }
+    if (DOT) {
+      const double s = bsum(ds, red);
+      if (tid == 0) partials[it] = s;
+    }
+  }
+}
+
+// Inner stage of the matvec for d = 2: A = M1 x, B = J1 x, C = K1 x along the
+// contiguous columns of n1 entries (chunks of kInChunk elements).
+__global__ __launch_bounds__(kT) void binner1_kernel(const double* __restrict__ x, double* __restrict__ A,
+                                                     double* __restrict__ Bo, double* __restrict__ C,
+                                                     const BProb* __restrict__ P, const Item* __restrict__ items,
+                                                     int nitems, const PcgScalars* __restrict__ S) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const Item I = items[it];
+    if (skip(S, I.prob)) continue;
+    const BProb& B = P[I.prob];
+    const int n1 = B.n[0], p = B.p[0], bw = 2 * p + 1;
+    const int e0 = I.idx * kInChunk, e1 = min(B.N, e0 + kInChunk);
+    const double* xp = x + B.off;
+    for (int e = e0 + threadIdx.x; e < e1; e += kT) {
+      const int i = e % n1, col0 = e - i;
+      double a = 0.0, b = 0.0, c = 0.0;
+      for (int o = 0; o < bw; ++o) {
+        const int j = i + o - p;
+        if (j < 0 || j >= n1) continue;
+        const double v = xp[col0 + j];
+        a += B.M[0][i * bw + o] * v;
+        b += B.J[0][i * bw + o] * v;
+        c += B.K[0][i * bw + o] * v;
+      }
+      A[B.off + e] = a;
+      Bo[B.off + e] = b;
+      C[B.off + e] = c;
+    }
+  }
+}
+
+// Outer stage (last space direction and time), same streaming scheme as the
+// single-problem kernel: per item 16 inner indices x Td rows of i_d x a chunk
+// of output time slices, register window of 2P+1 slices, fused final-time
+// term and fused partial dot product y . dotv.  P: degree in space and time.
+template <int PP>
+__global__ __launch_bounds__(kT) void bouter_kernel(const double* __restrict__ A, const double* __restrict__ Bi,
+                                                    const double* __restrict__ C, double* __restrict__ y,
+                                                    const BProb* __restrict__ P, const Item* __restrict__ items,
+                                                    int nitems, const PcgScalars* __restrict__ S,
+                                                    const double* __restrict__ dotv, double* __restrict__ partials) {
+  constexpr int W = 2 * PP + 1;
+  constexpr int ROWS = kOMaxTd + 2 * PP;
+  __shared__ double sbuf[2][3][ROWS * kOLb];
+  __shared__ double red[4];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const Item I = items[it];
+    if (skip(S, I.prob)) {
+      if (threadIdx.x == 0) partials[it] = 0.0;
+      continue;
+    }
+    const BProb& B = P[I.prob];
+    const int d = B.d;
+    const bool three = d == 2;
+    const int L = (d == 2) ? B.n[0] : 1;
+    const int nd = B.n[d - 1], nt = B.n[d];
+    const int Td = B.Td, rows = Td + 2 * PP;
+    const int td = I.idx % B.ntd, lb = (I.idx / B.ntd) % B.nlb, ch = I.idx / (B.ntd * B.nlb);
+    const int l0 = lb * kOLb, d0 = td * Td, c0 = ch * B.Tc, c1 = min(nt, c0 + B.Tc);
+    const int li = threadIdx.x % kOLb, di = threadIdx.x / kOLb;
+    const int l = l0 + li, id = d0 + di;
+    const bool mine = di < Td && l < L && id < nd;
+    const int dic = min(di, Td - 1), idc = min(id, nd - 1);
+    const size_t plane = (size_t)L * nd;
+    const double* Ap = A + B.off;
+    const double* Bp = three ? Bi + B.off : nullptr;
+    const double* Cp = three ? C + B.off : nullptr;
+    const double* Md = B.M[d - 1];
+    const double* Jd = B.J[d - 1];
+    const double* Kd = B.K[d - 1];
+    const double* Kt = B.K[d];
+    const double* Mt = B.M[d];
+    double cm[W], cj[W], ck[W];
+#pragma unroll
+    for (int o = 0; o < W; ++o) { cm[o] = Md[idc * W + o]; cj[o] = Jd[idc * W + o]; ck[o] = Kd[idc * W + o]; }
+    double S1w[W], S2w[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) { S1w[k] = 0.0; S2w[k] = 0.0; }
+    double S3 = 0.0, ds = 0.0;
+    const int tb = max(0, c0 - PP), te = c1 - 1 + PP;
+    for (int t = tb; t <= te; ++t) {
+      __syncthreads();
+      if (t < nt) {
+        for (int s = 0; s < kOSlots; ++s) {
+          const int rr = di + kOMaxTd * s;
+          const int row = d0 - PP + rr;
+          if (rr < rows) {
+            const bool ok = row >= 0 && row < nd && l < L;
+            const size_t g = (size_t)t * plane + (size_t)(ok ? row : 0) * L + (ok ? l : 0);
+            const double a = Ap[g];
+            sbuf[0][0][rr * kOLb + li] = ok ? a : 0.0;
+            if (three) {
+              const double bv = Bp[g], cv = Cp[g];
+              sbuf[0][1][rr * kOLb + li] = ok ? bv : 0.0;
+              sbuf[0][2][rr * kOLb + li] = ok ? cv : 0.0;
+            }
+          }
+        }
+      }
+      __syncthreads();
+      double s1 = 0.0, jA = 0.0, mB = 0.0, kC = 0.0, kA = 0.0, mC = 0.0;
+      if (t < nt) {
+#pragma unroll
+        for (int o = 0; o < W; ++o) {
+          const int rr = dic + o;
+          const double a = sbuf[0][0][rr * kOLb + li];
+          s1 += cm[o] * a;
+          jA += cj[o] * a;
+          kA += ck[o] * a;
+          if (three) {
+            const double bv = sbuf[0][1][rr * kOLb + li], cv = sbuf[0][2][rr * kOLb + li];
+            mB += cm[o] * bv;
+            kC += ck[o] * cv;
+            mC += cm[o] * cv;
+          }
+        }
+      }
+      if (t == nt - 1) S3 = B.kw * (kA + mC);
+#pragma unroll
+      for (int k = 0; k < W - 1; ++k) { S1w[k] = S1w[k + 1]; S2w[k] = S2w[k + 1]; }
+      S1w[W - 1] = s1;
+      S2w[W - 1] = B.k2 * (jA + mB + 2.0 * kC);
+      const int tp = t - PP;
+      if (tp >= c0 && tp < c1) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) v += Kt[tp * W + k] * S1w[k] + Mt[tp * W + k] * S2w[k];
+        if (tp == nt - 1) v += S3;
+        if (mine) {
+          const size_t g = (size_t)tp * plane + (size_t)id * L + l;
+          y[B.off + g] = v;
+          if (dotv) ds += v * dotv[B.off + g];
+        }
+      }
+    }
+    if (dotv) {
+      const double s = bsum(ds, red);
+      if (threadIdx.x == 0) partials[it] = s;
+    }
+  }
+}
+
+// vector kernels over (problem, chunk) items
+enum BVec { BV_DOT_BB = 0, BV_XR = 1, BV_P = 2, BV_INIT = 3 };
+__global__ __launch_bounds__(kT) void bvec_kernel(int kind, double* __restrict__ x, double* __restrict__ r,
+                                                  double* __restrict__ p, const double* __restrict__ q,
+                                                  const double* __restrict__ b, const BProb* __restrict__ P,
+                                                  const Item* __restrict__ items, int nitems,
+                                                  const PcgScalars* __restrict__ S, double* __restrict__ partials) {
+  __shared__ double red[4];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const Item I = items[it];
+    const BProb& B = P[I.prob];
+    const size_t e0 = B.off + (size_t)I.idx * kVecChunk;
+    const size_t e1 = B.off + std::min<size_t>((size_t)(I.idx + 1) * kVecChunk, (size_t)B.N);
+    double s = 0.0;
+    if (kind == BV_INIT) {  // x = 0, r = b; partial sums of b.b
+      for (size_t e = e0 + threadIdx.x; e < e1; e += kT) {
+        const double bv = b[e];
+        x[e] = 0.0;
+        r[e] = bv;
+        s += bv * bv;
+      }
+    } else if (!skip(S, I.prob)) {
+      if (kind == BV_XR) {
+        const double alpha = S[I.prob].alpha;
+        for (size_t e = e0 + threadIdx.x; e < e1; e += kT) {
+          x[e] += alpha * p[e];
+          const double rn = r[e] - alpha * q[e];
+          r[e] = rn;
+          s += rn * rn;
+        }
+      } else if (kind == BV_P) {  // p = z + beta p   (z passed in q)
+        const double beta = S[I.prob].beta;
+        for (size_t e = e0 + threadIdx.x; e < e1; e += kT) p[e] = q[e] + beta * p[e];
+      }
+    }
+    if (kind != BV_P) {
+      s = bsum(s, red);
+      if (threadIdx.x == 0) partials[it] = s;
+    }
+  }
+}
+
+__global__ void bcopy_kernel(double* __restrict__ dst, const double* __restrict__ src, const BProb* __restrict__ P,
+                             const Item* __restrict__ items, int nitems, const PcgScalars* __restrict__ S) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const Item I = items[it];
+    if (skip(S, I.prob)) continue;
+    const BProb& B = P[I.prob];
+    const size_t e0 = B.off + (size_t)I.idx * kVecChunk;
+    const size_t e1 = B.off + std::min<size_t>((size_t)(I.idx + 1) * kVecChunk, (size_t)B.N);
+    for (size_t e = e0 + threadIdx.x; e < e1; e += kT) dst[e] = src[e];
+  }
+}
+
+enum BFin { BF_BNORM = 0, BF_RHO0, BF_ALPHA, BF_RR, BF_BETA };
+// One workgroup per problem: fixed-order sum of the problem's partials
+// [beg[prob], end[prob]) and update of its scalars.
+__global__ __launch_bounds__(kT) void bfinalize_kernel(const double* __restrict__ partials, const int* __restrict__ beg,
+                                                       const int* __restrict__ end, PcgScalars* __restrict__ S,
+                                                       int kind, int iter, double rtol) {
+  __shared__ double red[4];
+  const int prob = blockIdx.x;
+  PcgScalars& s = S[prob];
+  if (kind == BF_BNORM && threadIdx.x == 0) {
+    s.rho = s.alpha = s.beta = 0.0;
+    s.relres = 1.0;
+    s.rtol = rtol;
+    s.done = s.flag = s.iters = 0;
+  }
+  __syncthreads();
+  if (s.done || s.flag) return;
+  double v = 0.0;
+  for (int i = beg[prob] + threadIdx.x; i < end[prob]; i += kT) v += partials[i];
+  const double t = bsum(v, red);
+  if (threadIdx.x != 0) return;
+  switch (kind) {
+    case BF_BNORM:
+      s.bnorm2 = t;
+      if (!isfinite(t)) s.flag = 2;
+      else if (t == 0.0) { s.done = 1; s.relres = 0.0; }
+      break;
+    case BF_RHO0:
+      s.rho = t;
+      if (!isfinite(t)) s.flag = 2; else if (!(t > 0.0)) s.flag = 1;
+      break;
+    case BF_ALPHA:
+      if (!isfinite(t)) s.flag = 2; else if (!(t > 0.0)) s.flag = 1; else s.alpha = s.rho / t;
+      break;
+    case BF_RR: {
+      const double rel = sqrt(t / s.bnorm2);
+      s.relres = rel;
+      s.iters = iter;
+      if (!isfinite(rel)) s.flag = 2; else if (rel <= s.rtol) s.done = 1;
+      break;
+    }
+    case BF_BETA:
+      if (!isfinite(t)) s.flag = 2; else if (!(t > 0.0)) s.flag = 1; else { s.beta = t / s.rho; s.rho = t; }
+      break;
+  }
+}
+
+template <typename T>
+int upload_vec(T** dst, const std::vector<T>& v, hipStream_t st) {
+  if (hipMalloc((void**)dst, std::max<size_t>(1, v.size()) * sizeof(T)) != hipSuccess) {
+    set_error("hipMalloc (batch)");
+    return STLS_ENOMEM;
+  }
+  if (!v.empty() && hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess) {
+    set_error("hipMemcpyAsync (batch)");
+    return STLS_EHIP;
+  }
+  return STLS_OK;
+}
+
+struct ItemList {
+  Item* dev = nullptr;
+  int count = 0;
+  int* beg = nullptr;  // per problem, into this list
+  int* end = nullptr;
+};
+
+}  // namespace
+
+}  // namespace stls
+
+using namespace stls;
+
+struct stls_batch_ctx {
+  int nprob = 0, d = 0;
+  hipStream_t stream = nullptr;
+  std::vector<stls_handle> probs;
+  std::vector<BProb> hdesc;
+  BProb* desc = nullptr;
+  std::vector<int64_t> off;  // nprob + 1
+  int64_t total = 0;
+  ItemList fd[4];       // FD passes per direction (index d = fused time)
+  ItemList vec, inner;
+  std::vector<ItemList> outer;   // per degree group
+  std::vector<int> outer_p;      // degree of each group
+  ItemList outer_all;            // concatenation (for the dot ranges)
+  std::vector<int> outer_base;   // item offset of each group within outer_all
+  double* buf[10] = {nullptr};   // r z p q fd0 fd1 A B C spare
+  double* partials = nullptr;
+  int partials_cap = 0;
+  PcgScalars* S = nullptr;
+  PcgScalars* Sh = nullptr;
+  std::vector<int> last_iters;
+};
+
+namespace {
+
+// make a list of items (prob, idx) for idx < count[prob]
+int make_list(stls_batch_ctx* B, ItemList& L, const std::vector<int>& count, const std::vector<int>* probs = nullptr) {
+  std::vector<Item> items;
+  std::vector<int> beg(B->nprob, 0), end(B->nprob, 0);
+  auto add = [&](int p) {
+    beg[p] = (int)items.size();
+    for (int i = 0; i < count[p]; ++i) items.push_back({p, i});
+    end[p] = (int)items.size();
+  };
+  if (probs) for (int p : *probs) add(p);
+  else for (int p = 0; p < B->nprob; ++p) add(p);
+  L.count = (int)items.size();
+  int st = upload_vec(&L.dev, items, B->stream);
+  if (!st) st = upload_vec(&L.beg, beg, B->stream);
+  if (!st) st = upload_vec(&L.end, end, B->stream);
+  return st;
+}
+
+void free_list(ItemList& L) {
+  if (L.dev) (void)hipFree(L.dev);
+  if (L.beg) (void)hipFree(L.beg);
+  if (L.end) (void)hipFree(L.end);
+  L = ItemList();
+}
+
+void free_batch(stls_batch_ctx* B) {
+  if (!B) return;
+  for (auto& L : B->fd) free_list(L);
+  free_list(B->vec);
+  free_list(B->inner);
+  for (auto& L : B->outer) free_list(L);
+  free_list(B->outer_all);
+  for (double* p : B->buf)
+    if (p) (void)hipFree(p);
+  if (B->partials) (void)hipFree(B->partials);
+  if (B->S) (void)hipFree(B->S);
+  if (B->Sh) (void)hipHostFree(B->Sh);
+  if (B->desc) (void)hipFree(B->desc);
+  for (auto h : B->probs)
+    if (h) stls_destroy(h);
+  delete B;
+}
+
+int grid_items(int n) { return std::max(1, std::min(n, 256 * 8)); }
+
+int bfin(stls_batch_ctx* B, const ItemList& L, int kind, int iter, double rtol) {
+  hipLaunchKernelGGL(bfinalize_kernel, dim3(B->nprob), dim3(kT), 0, B->stream, B->partials, L.beg, L.end, B->S, kind,
+                     iter, rtol);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? STLS_OK : hip_fail(e, "bfinalize_kernel launch");
+}
+
+int bprec(stls_batch_ctx* B, const double* r, double* s, const double* dotv) {
+  const int d = B->d;
+  double* f0 = B->buf[4];
+  double* f1 = B->buf[5];
+  const double* in = r;
+  double* outs[2] = {f0, f1};
+  int cur = 0;
+  hipStream_t st = B->stream;
+  // forward space modes
+  for (int k = 0; k < d; ++k) {
+    double* out = outs[cur];
+    if (k == 0)
+      hipLaunchKernelGGL((bfd_kernel<true, false, false>), dim3(grid_items(B->fd[k].count)), dim3(kT), 0, st, in, out,
+                         B->desc, B->fd[k].dev, B->fd[k].count, k, 0, B->S, nullptr, nullptr);
+    else
+      hipLaunchKernelGGL((bfd_kernel<false, false, false>), dim3(grid_items(B->fd[k].count)), dim3(kT), 0, st, in, out,
+                         B->desc, B->fd[k].dev, B->fd[k].count, k, 0, B->S, nullptr, nullptr);
+    in = out;
+    cur ^= 1;
+  }
+  hipLaunchKernelGGL((bfd_kernel<false, true, false>), dim3(grid_items(B->fd[d].count)), dim3(kT), 0, st, in,
+                     outs[cur], B->desc, B->fd[d].dev, B->fd[d].count, d, 0, B->S, nullptr, nullptr);
+  in = outs[cur];
+  cur ^= 1;
+  for (int k = d - 1; k >= 0; --k) {
+    double* out = (k == 0) ? s : outs[cur];
+    if (k == 0) {
+      if (dotv)
+        hipLaunchKernelGGL((bfd_kernel<true, false, true>), dim3(grid_items(B->fd[k].count)), dim3(kT), 0, st, in, out,
+                           B->desc, B->fd[k].dev, B->fd[k].count, k, 1, B->S, dotv, B->partials);
+      else
+        hipLaunchKernelGGL((bfd_kernel<true, false, false>), dim3(grid_items(B->fd[k].count)), dim3(kT), 0, st, in,
+                           out, B->desc, B->fd[k].dev, B->fd[k].count, k, 1, B->S, nullptr, nullptr);
+    } else {
+      hipLaunchKernelGGL((bfd_kernel<false, false, false>), dim3(grid_items(B->fd[k].count)), dim3(kT), 0, st, in,
+                         out, B->desc, B->fd[k].dev, B->fd[k].count, k, 1, B->S, nullptr, nullptr);
+    }
+    in = out;
+    cur ^= 1;
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? STLS_OK : hip_fail(e, "batched FD launch");
+}
+
+int bmatvec(stls_batch_ctx* B, const double* x, double* y, const double* dotv) {
+  hipStream_t st = B->stream;
+  const double* A = x;
+  const double* Bv = nullptr;
+  const double* C = nullptr;
+  if (B->d == 2) {
+    hipLaunchKernelGGL(binner1_kernel, dim3(grid_items(B->inner.count)), dim3(kT), 0, st, x, B->buf[6], B->buf[7],
+                       B->buf[8], B->desc, B->inner.dev, B->inner.count, B->S);
+    A = B->buf[6];
+    Bv = B->buf[7];
+    C = B->buf[8];
+  }
+  for (size_t g = 0; g < B->outer.size(); ++g) {
+    const ItemList& L = B->outer[g];
+    if (L.count == 0) continue;
+    double* parts = B->partials + B->outer_base[g];
+    void (*kern)(const double*, const double*, const double*, double*, const BProb*, const Item*, int,
+                 const PcgScalars*, const double*, double*) = nullptr;
+    switch (B->outer_p[g]) {
+      case 1: kern = bouter_kernel<1>; break;
+      case 2: kern = bouter_kernel<2>; break;
+      case 3: kern = bouter_kernel<3>; break;
+      case 4: kern = bouter_kernel<4>; break;
+      case 5: kern = bouter_kernel<5>; break;
+      case 6: kern = bouter_kernel<6>; break;
+      default: set_error("batch degree not supported"); return STLS_EINVAL;
+    }
+    hipLaunchKernelGGL(kern, dim3(grid_items(L.count)), dim3(kT), 0, st, A, Bv, C, y, B->desc, L.dev, L.count, B->S,
+                       dotv, parts);
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? STLS_OK : hip_fail(e, "batched matvec launch");
+}
+
+int read_scalars(stls_batch_ctx* B) {
+  hipError_t e = hipMemcpyAsync(B->Sh, B->S, sizeof(PcgScalars) * B->nprob, hipMemcpyDeviceToHost, B->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  e = hipStreamSynchronize(B->stream);
+  return e == hipSuccess ? STLS_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+}  // namespace
+
+extern "C" {
+
+int stls_batch_setup(int nprob, int d, const int* nknots, const double* const* knots, const int* degree,
+                     const double* kappa, void* stream, stls_batch_handle* out) {
+  if (!out) { set_error("out is NULL"); return STLS_EINVAL; }
+  *out = nullptr;
+  if (nprob < 1 || (d != 1 && d != 2) || !nknots || !knots || !degree || !kappa) {
+    set_error("batch: nprob >= 1, d in {1, 2} and non-NULL arrays required");
+    return STLS_EINVAL;
+  }
+  for (int i = 0; i < nprob; ++i)
+    for (int k = 1; k <= d; ++k)
+      if (degree[i * (d + 1) + k] != degree[i * (d + 1)] || degree[i * (d + 1)] > 6) {
+        set_error("batch: every problem needs the same degree (<= 6) in all directions");
+        return STLS_EINVAL;
+      }
+  stls_batch_ctx* B = new stls_batch_ctx();
+  B->nprob = nprob;
+  B->d = d;
+  B->stream = (hipStream_t)stream;
+  B->probs.assign(nprob, nullptr);
+  // per-problem setup (host quadrature and eigensolves) in parallel threads
+  std::vector<int> status(nprob, STLS_OK);
+  std::vector<std::string> errs(nprob);
+  const int nthreads = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nthreads; ++t)
+    pool.emplace_back([&, t]() {
+      for (int i = t; i < nprob; i += nthreads) {
+        status[i] = stls_setup(d, nknots + i * (d + 1), knots + i * (d + 1), degree + i * (d + 1), kappa[i], stream,
+                               &B->probs[i]);
+        if (status[i]) errs[i] = stls_last_error();
+      }
+    });
+  for (auto& th : pool) th.join();
+  for (int i = 0; i < nprob; ++i)
+    if (status[i]) {
+      set_error("batch problem " + std::to_string(i) + ": " + errs[i]);
+      const int st = status[i];
+      free_batch(B);
+      return st;
+    }
+  // descriptors, offsets, work lists
+  B->off.assign(nprob + 1, 0);
+  B->hdesc.resize(nprob);
+  std::vector<int> cnt_vec(nprob), cnt_in(nprob), cnt_fd[4];
+  for (int k = 0; k <= d; ++k) cnt_fd[k].assign(nprob, 0);
+  std::vector<int> cnt_outer(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    stls_ctx* h = B->probs[i];
+    BProb& P = B->hdesc[i];
+    std::memset(&P, 0, sizeof(P));
+    P.off = B->off[i];
+    P.N = (int)h->ndof;
+    P.ns = (int)h->ns;
+    P.d = d;
+    for (int k = 0; k <= d; ++k) {
+      const DevDir& D = h->dd[k];
+      if (D.n > kBNM * 16) {
+        set_error("batch: directions are limited to n <= 112");
+        free_batch(B);
+        return STLS_EINVAL;
+      }
+      P.n[k] = D.n;
+      P.p[k] = D.p;
+      P.npad[k] = D.npad;
+      P.Af[k] = D.Afwd64;
+      P.Ab[k] = D.Abwd64;
+      P.M[k] = D.M;
+      P.K[k] = D.K;
+      P.J[k] = D.J;
+      cnt_fd[k][i] = (P.N / D.n + kBCols - 1) / kBCols;
+    }
+    cnt_fd[d][i] = (P.ns + kBCols - 1) / kBCols;  // fused time: one column per spatial index
+    P.lam_t = h->dd[d].lam;
+    P.lam_s = h->lam_s;
+    P.k2 = h->kappa * h->kappa;
+    P.kw = h->kappa * h->dir[d].wend;
+    const int L = d == 2 ? P.n[0] : 1, nd = P.n[d - 1], nt = P.n[d];
+    P.ntd = (nd + kOMaxTd - 1) / kOMaxTd;
+    P.Td = (nd + P.ntd - 1) / P.ntd;
+    P.nlb = (L + kOLb - 1) / kOLb;
+    P.nchunk = 1;
+    P.Tc = nt;
+    cnt_outer[i] = P.nlb * P.ntd * P.nchunk;
+    cnt_vec[i] = (P.N + kVecChunk - 1) / kVecChunk;
+    cnt_in[i] = (P.N + kInChunk - 1) / kInChunk;
+    B->off[i + 1] = B->off[i] + P.N;
+  }
+  B->total = B->off[nprob];
+  int st = upload_vec(&B->desc, B->hdesc, B->stream);
+  for (int k = 0; k <= d && !st; ++k) st = make_list(B, B->fd[k], cnt_fd[k]);
+  if (!st) st = make_list(B, B->vec, cnt_vec);
+  if (!st && d == 2) st = make_list(B, B->inner, cnt_in);
+  // outer items grouped by degree; the concatenated list fixes the partial ranges
+  if (!st) {
+    std::vector<int> degs;
+    for (int i = 0; i < nprob; ++i) degs.push_back(B->hdesc[i].p[0]);
+    std::vector<int> uniq(degs);
+    std::sort(uniq.begin(), uniq.end());
+    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    std::vector<int> order;
+    int base = 0;
+    for (int p : uniq) {
+      std::vector<int> members;
+      for (int i = 0; i < nprob; ++i)
+        if (degs[i] == p) members.push_back(i);
+      ItemList L;
+      if ((st = make_list(B, L, cnt_outer, &members))) break;
+      B->outer.push_back(L);
+      B->outer_p.push_back(p);
+      B->outer_base.push_back(base);
+      base += L.count;
+      for (int m : members) order.push_back(m);
+    }
+    if (!st) st = make_list(B, B->outer_all, cnt_outer, &order);
+  }
+  int cap = 0;
+  for (int k = 0; k <= d; ++k) cap = std::max(cap, B->fd[k].count);
+  cap = std::max({cap, B->vec.count, B->outer_all.count, 1});
+  B->partials_cap = cap;
+  if (!st && hipMalloc((void**)&B->partials, sizeof(double) * cap) != hipSuccess) { set_error("hipMalloc"); st = STLS_ENOMEM; }
+  for (int i = 0; i < 9 && !st; ++i)
+    if (hipMalloc((void**)&B->buf[i], sizeof(double) * std::max<int64_t>(1, B->total)) != hipSuccess) {
+      set_error("hipMalloc batch vectors");
+      st = STLS_ENOMEM;
+    }
+  if (!st && hipMalloc((void**)&B->S, sizeof(PcgScalars) * nprob) != hipSuccess) { set_error("hipMalloc"); st = STLS_ENOMEM; }
+  if (!st && hipHostMalloc((void**)&B->Sh, sizeof(PcgScalars) * nprob, hipHostMallocDefault) != hipSuccess) {
+    set_error("hipHostMalloc");
+    st = STLS_ENOMEM;
+  }
+  if (!st && hipMemsetAsync(B->S, 0, sizeof(PcgScalars) * nprob, B->stream) != hipSuccess) st = STLS_EHIP;
+  if (!st && hipStreamSynchronize(B->stream) != hipSuccess) st = STLS_EHIP;
+  if (st) {
+    free_batch(B);
+    return st;
+  }
+  B->last_iters.assign(nprob, 0);
+  *out = B;
+  return STLS_OK;
+}
+
+int stls_batch_destroy(stls_batch_handle B) {
+  if (!B) return STLS_OK;
+  (void)hipStreamSynchronize(B->stream);
+  free_batch(B);
+  return STLS_OK;
+}
+
+int stls_batch_offsets(stls_batch_handle B, int64_t* off) {
+  if (!B || !off) { set_error("bad batch handle or pointer"); return STLS_EINVAL; }
+  for (int i = 0; i <= B->nprob; ++i) off[i] = B->off[i];
+  return STLS_OK;
+}
+
+int stls_batch_problem(stls_batch_handle B, int i, stls_handle* h) {
+  if (!B || !h || i < 0 || i >= B->nprob) { set_error("bad batch handle or index"); return STLS_EINVAL; }
+  *h = B->probs[i];
+  return STLS_OK;
+}
+
+int stls_batch_matvec(stls_batch_handle B, const double* x, double* y) {
+  if (!B || !x || !y || x == y) { set_error("bad batch handle or pointers"); return STLS_EINVAL; }
+  hipMemsetAsync(B->S, 0, sizeof(PcgScalars) * B->nprob, B->stream);  // no problem is masked
+  return bmatvec(B, x, y, nullptr);
+}
+
+int stls_batch_prec_apply(stls_batch_handle B, const double* r, double* s) {
+  if (!B || !r || !s || r == s) { set_error("bad batch handle or pointers"); return STLS_EINVAL; }
+  hipMemsetAsync(B->S, 0, sizeof(PcgScalars) * B->nprob, B->stream);
+  return bprec(B, r, s, nullptr);
+}
+
+int stls_batch_pcg_solve(stls_batch_handle B, const double* b, double* x, double rtol, int maxit, int* iters,
+                         double* relres) {
+  if (!B || !b || !x || b == x || !(rtol > 0.0) || maxit < 1) { set_error("bad batch arguments"); return STLS_EINVAL; }
+  hipStream_t st = B->stream;
+  double* r = B->buf[0];
+  double* z = B->buf[1];
+  double* p = B->buf[2];
+  double* q = B->buf[3];
+  int s;
+  const int gv = grid_items(B->vec.count);
+  hipLaunchKernelGGL(bvec_kernel, dim3(gv), dim3(kT), 0, st, (int)BV_INIT, x, r, p, q, b, B->desc, B->vec.dev,
+                     B->vec.count, B->S, B->partials);
+  if ((s = bfin(B, B->vec, BF_BNORM, 0, rtol))) return s;
+  if ((s = bprec(B, r, z, r))) return s;
+  if ((s = bfin(B, B->fd[0], BF_RHO0, 0, rtol))) return s;
+  hipLaunchKernelGGL(bcopy_kernel, dim3(gv), dim3(kT), 0, st, p, z, B->desc, B->vec.dev, B->vec.count, B->S);
+  int status = STLS_ENOCONV;
+  for (int k = 1; k <= maxit; ++k) {
+    if ((s = bmatvec(B, p, q, p))) return s;
+    if ((s = bfin(B, B->outer_all, BF_ALPHA, k, rtol))) return s;
+    hipLaunchKernelGGL(bvec_kernel, dim3(gv), dim3(kT), 0, st, (int)BV_XR, x, r, p, q, b, B->desc, B->vec.dev,
+                       B->vec.count, B->S, B->partials);
+    if ((s = bfin(B, B->vec, BF_RR, k, rtol))) return s;
+    if ((s = read_scalars(B))) return s;
+    bool all = true, bad = false;
+    for (int i = 0; i < B->nprob; ++i) {
+      if (B->Sh[i].flag) bad = true;
+      else if (!B->Sh[i].done) all = false;
+    }
+    if (all) { status = bad ? STLS_EBREAKDOWN : STLS_OK; break; }
+    if (k == maxit) break;
+    if ((s = bprec(B, r, z, r))) return s;
+    if ((s = bfin(B, B->fd[0], BF_BETA, k, rtol))) return s;
+    hipLaunchKernelGGL(bvec_kernel, dim3(gv), dim3(kT), 0, st, (int)BV_P, x, r, p, z, b, B->desc, B->vec.dev,
+                       B->vec.count, B->S, B->partials);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "batched PCG launch");
+  if ((s = read_scalars(B))) return s;
+  bool nan = false;
+  for (int i = 0; i < B->nprob; ++i) {
+    if (iters) iters[i] = B->Sh[i].iters;
+    if (relres) relres[i] = B->Sh[i].relres;
+    B->last_iters[i] = B->Sh[i].iters;
+    if (B->Sh[i].flag == 2) nan = true;
+  }
+  if (nan) { set_error("non-finite value in a batched problem"); return STLS_ENAN; }
+  if (status == STLS_ENOCONV) set_error("some batched problems did not reach rtol within maxit");
+  return status;
+}
+
+}  // extern "C"

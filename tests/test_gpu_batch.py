@@ -1,0 +1,104 @@
+"""Batched PCG over many uneven problems (one launch per PCG step).
+
+Invariant: each problem of a batch gives the same result as its standalone
+solve on the same factors (batched kernels reduce in a different order:
+operators agree to 1e-12 relative, solves to the tolerance, iteration counts
+within one).  The smallest problem is also compared with the oracle.
+"""
+import numpy as np
+import pytest
+
+from stls_inputs import batch_params, batch_problem_knots, problem_knots, uniform_pm1
+
+pytestmark = pytest.mark.gpu
+
+try:
+    import paper_1809_10026_amd as stls
+except ImportError:
+    stls = None
+
+from oracle import fd as ofd, pcg as opcg, system as osys  # noqa: E402
+from tests.gpu_util import rel_err, to_dev, to_host  # noqa: E402
+
+SMALL = [
+    ((7, 9, 8), 2, 0.3),
+    ((12, 5, 10), 3, 1.0),
+    ((6, 6, 13), 4, 5.0),
+    ((9, 11, 7), 5, 0.12),
+    ((16, 18, 17), 3, 2.2),
+]
+
+
+def _batch(specs):
+    assert stls is not None, "libstls.so is not built"
+    probs = []
+    for nel, p, kappa in specs:
+        knots, degs = problem_knots(2, list(nel), p)
+        probs.append((knots, degs, kappa))
+    return stls.Batch(probs), probs
+
+
+def _single(B, i, probs):
+    knots, degs, kappa = probs[i]
+    return stls.Solver(knots, degs, kappa=kappa)
+
+
+def test_batched_operators_match_single_problem():
+    import torch
+    B, probs = _batch(SMALL)
+    off = B.offsets
+    x = to_dev(uniform_pm1(B.total, 61))
+    y = B.matvec(x)
+    s = B.prec_apply(x)
+    for i in range(len(probs)):
+        S = _single(B, i, probs)
+        xi = x[off[i]:off[i + 1]].contiguous()
+        assert rel_err(to_host(y[off[i]:off[i + 1]]), to_host(S.matvec(xi))) < 1e-13
+        # same factors would need the batch's own handle: compare with the oracle FD instead
+        P = osys.Problem(*problem_knots(2, list(SMALL[i][0]), SMALL[i][1]), kappa=SMALL[i][2])
+        s_ref = osys.vec(ofd.FD(P).apply(to_host(xi)))
+        assert rel_err(to_host(s[off[i]:off[i + 1]]), s_ref) < 1e-10
+
+
+def test_batched_solve_matches_single_and_oracle():
+    B, probs = _batch(SMALL)
+    off = B.offsets
+    b = to_dev(uniform_pm1(B.total, 62))
+    x, its, rels = B.solve(b, rtol=1e-8, maxit=300)
+    assert all(r <= 1e-8 for r in rels)
+    for i in range(len(probs)):
+        S = _single(B, i, probs)
+        xs, it_s, rel_s = S.solve(b[off[i]:off[i + 1]].contiguous(), rtol=1e-8)
+        assert abs(its[i] - it_s) <= 1
+        assert rel_err(to_host(x[off[i]:off[i + 1]]), to_host(xs)) < 1e-7
+    # smallest problem against the oracle
+    i = 0
+    P = osys.Problem(*problem_knots(2, list(SMALL[i][0]), SMALL[i][1]), kappa=SMALL[i][2])
+    bi = to_host(b[off[i]:off[i + 1]])
+    fdo = ofd.FD(P)
+    xr, info = opcg.pcg(lambda v: osys.vec(P.matvec(v)), lambda v: osys.vec(fdo.apply(v)), bi, 1e-8)
+    assert abs(its[i] - info["iters"]) <= 1
+    assert rel_err(to_host(x[off[i]:off[i + 1]]), xr) < 1e-6
+
+
+def test_full_uneven_batch_converges():
+    """256 problems: n_el per direction uniform on 16..96, p uniform on {2..5},
+    kappa log-uniform on [0.1, 10], right-hand sides U[-1,1] (seeds 20180927 + i)."""
+    nel, p, kappa = batch_params()
+    probs = []
+    for i in range(len(p)):
+        knots, degs = batch_problem_knots(nel[i], p[i])
+        probs.append((knots, degs, float(kappa[i])))
+    B = stls.Batch(probs)
+    off = B.offsets
+    b = np.concatenate([uniform_pm1(off[i + 1] - off[i], 20180927 + i) for i in range(len(probs))])
+    bt = to_dev(b)
+    x, its, rels = B.solve(bt, rtol=1e-8, maxit=500)
+    assert len(its) == 256 and max(rels) <= 1e-8 and min(its) >= 1
+    # batch invariant on sampled problems: standalone solves agree
+    for i in (0, 97, 255):
+        knots, degs, kap = probs[i]
+        S = stls.Solver(knots, degs, kappa=kap)
+        xs, it_s, _ = S.solve(bt[off[i]:off[i + 1]].contiguous(), rtol=1e-8)
+        assert abs(its[i] - it_s) <= 1
+        assert rel_err(to_host(x[off[i]:off[i + 1]]), to_host(xs)) < 1e-6
