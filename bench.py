@@ -60,8 +60,8 @@ def main():
     ap.add_argument("--maxit", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the solver is a single-GPU build (multi-GPU sharding is "
-              "described in DESIGN.md, not implemented); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the solver runs on a single GPU (sharding across GPUs is a "
+              "design note, not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -70,7 +70,7 @@ def main():
     import paper_1809_10026_amd as stls
     from stls_inputs import CONFIGS, problem_knots, uniform_pm1
 
-    cfg = CONFIGS["cfg3_d3_p4_nel48"]
+    cfg = CONFIGS["d3_p4_nel48"]
     d, nel, p, rtol = cfg["d"], cfg["n_el"], cfg["p"], cfg["rtol"]
     knots, degs = problem_knots(d, nel, p)
     torch.cuda.init()

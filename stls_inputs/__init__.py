@@ -58,10 +58,10 @@ def uniform_pm1(n: int, seed: int) -> np.ndarray:
 # Workload shapes of the paper-sized configurations (unit box, T = 1,
 # p_s = p_t = p, uniform open knots, homogeneous data).
 CONFIGS = {
-    "cfg1_d1_p2_nel32": dict(d=1, n_el=32, p=2, rtol=1e-10),
-    "cfg2_d2_p3_nel64": dict(d=2, n_el=64, p=3, rtol=1e-8, seed=1809),
-    "cfg3_d3_p4_nel48": dict(d=3, n_el=48, p=4, rtol=1e-8, seed=10026),
-    "cfg5_d2_p3_nel128": dict(d=2, n_el=128, p=3, rtol=1e-8, seed_f=5, seed_target=6, seed_dir=7),
+    "d1_p2_nel32_manufactured": dict(d=1, n_el=32, p=2, rtol=1e-10),
+    "d2_p3_nel64": dict(d=2, n_el=64, p=3, rtol=1e-8, seed=1809),
+    "d3_p4_nel48": dict(d=3, n_el=48, p=4, rtol=1e-8, seed=10026),
+    "d2_p3_nel128_gradient": dict(d=2, n_el=128, p=3, rtol=1e-8, seed_f=5, seed_target=6, seed_dir=7),
 }
 
 
