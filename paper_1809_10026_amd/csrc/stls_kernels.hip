@@ -1020,6 +1020,363 @@ __global__ __launch_bounds__(kThreads) void mv_outer_kernel(
   }
 }
 
+// Inner stage, d = 3, one whole (i3, t) slab per work item (n1, n2 <= 64).
+// The slab of x is kept transposed in LDS (xT[i1][i2]) so that the
+// direction-1 products run with lanes along i2 and a wave-uniform run of R1
+// columns i1: the band coefficients of those columns are uniform and come
+// through scalar loads, and the R1 + 2P input columns are read once for R1
+// outputs.  The direction-2 products run with lanes along i1 (coalesced
+// stores) and a wave-uniform run of R2 rows, again with scalar coefficients.
+// Both band operators are applied with clamped, branch-free taps: entries
+// outside the matrix are stored as zeros.  The next slab of x is fetched into
+// registers while the current one is processed.
+constexpr int kSlabWaves = 8;
+constexpr int kSlabR1 = 7;
+constexpr int kSlabR2 = 2;
+
+template <int P>
+__global__ __launch_bounds__(kSlabWaves * 64) void mv_inner_slab_kernel(
+    const double* __restrict__ x, double* __restrict__ A, double* __restrict__ B, double* __restrict__ C, int n1,
+    int n2, int nslab, int ld, const double* __restrict__ M1, const double* __restrict__ J1,
+    const double* __restrict__ K1, const double* __restrict__ M2, const double* __restrict__ J2,
+    const double* __restrict__ K2) {
+  constexpr int BW = 2 * P + 1;
+  constexpr int NW = kSlabWaves, R1 = kSlabR1, R2 = kSlabR2;
+  constexpr int PF = 64 / NW;  // rows of the slab fetched per wave (n2 <= 64)
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* xT = reinterpret_cast<double*>(smem_raw);  // n1 x n2
+  double* XM = xT + n1 * n2;                         // n2 x ld each
+  double* XJ = XM + n2 * ld;
+  double* XK = XJ + n2 * ld;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ns = n1 * n2;
+  const int i1l = min(lane, n1 - 1);
+  double pf[PF];
+  auto fetch = [&](int s) {
+    const double* xs = x + (size_t)s * ns;
+#pragma unroll
+    for (int k = 0; k < PF; ++k) pf[k] = xs[min(wave + NW * k, n2 - 1) * n1 + i1l];
+  };
+  int s = blockIdx.x;
+  if (s < nslab) fetch(s);
+  const int nb1 = (n1 + R1 - 1) / R1;
+  const int nb2 = (n2 + R2 - 1) / R2;
+  const int i2 = lane, i2c = min(lane, n2 - 1);
+  for (; s < nslab; s += gridDim.x) {
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int row = wave + NW * k;
+      if (row < n2 && lane < n1) xT[lane * n2 + row] = pf[k];
+    }
+    __syncthreads();
+    if (s + (int)gridDim.x < nslab) fetch(s + gridDim.x);
+    // direction 1: XM = M1 x, XJ = J1 x, XK = K1 x along i1
+    for (int it = wave; it < nb1; it += NW) {
+      const int c0 = it * R1;
+      double v[R1 + 2 * P];
+#pragma unroll
+      for (int j = 0; j < R1 + 2 * P; ++j) v[j] = xT[min(max(c0 - P + j, 0), n1 - 1) * n2 + i2c];
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        const int c = min(c0 + r, n1 - 1);
+        const double* cm = M1 + c * BW;
+        const double* cj = J1 + c * BW;
+        const double* ck = K1 + c * BW;
+        double m = 0.0, jj = 0.0, kk = 0.0;
+#pragma unroll
+        for (int o = 0; o < BW; ++o) {
+          m += cm[o] * v[r + o];
+          jj += cj[o] * v[r + o];
+          kk += ck[o] * v[r + o];
+        }
+        if (i2 < n2 && c0 + r < n1) {
+          XM[i2 * ld + c] = m;
+          XJ[i2 * ld + c] = jj;
+          XK[i2 * ld + c] = kk;
+        }
+      }
+    }
+    __syncthreads();
+    // direction 2: A = M2 XM, B = J2 XM + M2 XJ + 2 K2 XK, C = K2 XM + M2 XK along i2
+    const size_t base = (size_t)s * ns;
+    for (int it = wave; it < nb2; it += NW) {
+      const int r0 = it * R2;
+      double m[R2 + 2 * P], jv[R2 + 2 * P], kv[R2 + 2 * P];
+#pragma unroll
+      for (int j = 0; j < R2 + 2 * P; ++j) {
+        const int row = min(max(r0 - P + j, 0), n2 - 1);
+        m[j] = XM[row * ld + i1l];
+        jv[j] = XJ[row * ld + i1l];
+        kv[j] = XK[row * ld + i1l];
+      }
+#pragma unroll
+      for (int r = 0; r < R2; ++r) {
+        const int rr = min(r0 + r, n2 - 1);
+        const double* cm = M2 + rr * BW;
+        const double* cj = J2 + rr * BW;
+        const double* ck = K2 + rr * BW;
+        double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+        for (int o = 0; o < BW; ++o) {
+          a += cm[o] * m[r + o];
+          b += cj[o] * m[r + o] + cm[o] * jv[r + o] + 2.0 * ck[o] * kv[r + o];
+          c += ck[o] * m[r + o] + cm[o] * kv[r + o];
+        }
+        if (lane < n1 && r0 + r < n2) {
+          const size_t g = base + (size_t)(r0 + r) * n1 + lane;
+          A[g] = a;
+          B[g] = b;
+          C[g] = c;
+        }
+      }
+    }
+  }
+}
+
+// Outer stage with a direct-to-LDS load pipeline.  Workgroup = 4 waves, one
+// (l, i_d) pencil per thread (16 consecutive l x up to 16 rows i_d); it walks
+// the time slices of its chunk.  Each time slice of A, B, C (rows
+// d0-P .. d0+Td+P-1) and the slice t-PT of the dot operand are copied
+// global -> LDS by global_load_lds (16 B per lane, 8 rows of 16 l per wave
+// instruction) into a ring of kDmaSlots slots, kDmaSlots-1 slices ahead of
+// use.  Every wave issues exactly K copies per slice (surplus copies land in
+// a trash block), so that "slice t has arrived" is s_waitcnt vmcnt((D-2) K):
+// loads return in issue order, and only the copies of later slices may still
+// be outstanding.  Lanes past the staged rows read the first row of their
+// copy (a cache line that is fetched anyway).  Requires L even (16 B source
+// alignment of l pairs).
+//   space (i_d): s1 = M_d A, s2 = kappa^2 (J_d A + M_d B + 2 K_d C)
+//   time:        y(t') = sum_t K_t(t', t) s1(t) + M_t(t', t) s2(t), scattered
+//                into 2 PT + 1 accumulators as slice t arrives
+//   final time:  y(T) += kappa w (K_d A + M_d C)(T)
+typedef __attribute__((address_space(3))) void lds_void_t;
+constexpr int kDmaSlots = 4;
+constexpr int kDmaLb = 16;
+
+template <int N>
+__device__ inline void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  // gfx9 s_waitcnt: vmcnt in bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their maxima
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+template <int PT, int P, int K, bool DOT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void mv_outer_dma_kernel(
+    const double* __restrict__ A, const double* __restrict__ B, const double* __restrict__ C, double* __restrict__ y,
+    int L, int nd, int nt, int Td, int nlb, int ntd, int nchunk, int Tc, const double* __restrict__ Md,
+    const double* __restrict__ Jd, const double* __restrict__ Kd, const double* __restrict__ Kt,
+    const double* __restrict__ Mt, double k2, double kw, const double* __restrict__ dotv,
+    double* __restrict__ partials) {
+  constexpr int W = 2 * PT + 1;
+  constexpr int BW = 2 * P + 1;
+  constexpr int LB = kDmaLb;
+  constexpr int D = kDmaSlots;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* sm = reinterpret_cast<double*>(smem_raw);
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // row tiles fastest: the tiles sharing halo rows run together on one XCD
+  const int ntile = nlb * ntd * nchunk;
+  const int tile = xcd_tile(blockIdx.x, ntile);
+  const int td = tile % ntd;
+  const int lb = (tile / ntd) % nlb;
+  const int ch = tile / (nlb * ntd);
+  const int li = lane & 15, dr = 4 * wave + (lane >> 4);
+  const int l0 = lb * LB;
+  const int l = l0 + li, lc = min(l, L - 1);
+  const int d0 = td * Td, d1 = min(nd, d0 + Td);
+  const int row = d0 + dr, rowc = min(row, nd - 1), drc = min(dr, Td - 1);
+  double cm[BW], cj[BW], ck[BW];
+#pragma unroll
+  for (int o = 0; o < BW; ++o) {
+    cm[o] = Md[rowc * BW + o];
+    cj[o] = Jd[rowc * BW + o];
+    ck[o] = Kd[rowc * BW + o];
+  }
+  const int rows = Td + 2 * P;
+  const int rb8 = (rows + 7) >> 3;          // 8-row blocks per input array
+  const int rbd = DOT ? (Td + 7) >> 3 : 0;  // 8-row blocks of the dot operand
+  const int arr = rb8 * 8 * LB;             // doubles per input array in a slot
+  const int slot = 3 * arr + rbd * 8 * LB + 8 * LB;  // + trash block
+  const int njob = 3 * rb8 + rbd;
+  const bool mine = l < L && dr < Td && row < d1;
+  const int c0 = ch * Tc, c1 = min(nt, c0 + Tc);
+  const size_t plane = (size_t)L * nd;
+  const double* jsrc[K];
+  int jdst[K], jsh[K];
+  {
+    const int lp = lane & 7, lr = lane >> 3;
+    const int ls = min(l0 + 2 * lp, L - 2);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int jr = wave + 4 * k;
+      const bool dup = jr >= njob;
+      const int j = min(jr, njob - 1);
+      const int q = j < 3 * rb8 ? j / rb8 : 3;
+      const int rb = j - q * rb8;
+      const int nr = q < 3 ? rows : Td;
+      const bool pad = dup || rb * 8 + lr >= nr;
+      const int rr = pad ? rb * 8 : rb * 8 + lr;
+      const int lsx = pad ? min(l0, L - 2) : ls;
+      const int gr = q < 3 ? min(max(d0 - P + rr, 0), nd - 1) : min(d0 + rr, nd - 1);
+      const double* base = q == 0 ? A : (q == 1 ? B : (q == 2 ? C : dotv));
+      jsrc[k] = base + (size_t)gr * L + lsx;
+      jdst[k] = dup ? 3 * arr + rbd * 8 * LB : q * arr + rb * 8 * LB;
+      jsh[k] = q == 3 ? PT : 0;
+    }
+  }
+  auto issue = [&](int t, int sl) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const size_t toff = (size_t)min(max(t - jsh[k], 0), nt - 1) * plane;
+      __builtin_amdgcn_global_load_lds((const void*)(jsrc[k] + toff), (lds_void_t*)(sm + sl * slot + jdst[k]), 16,
+                                       0, 0);
+    }
+  };
+  double acc[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) acc[k] = 0.0;
+  double s3 = 0.0, dsum = 0.0;
+  const int tb = max(0, c0 - PT);
+  const int te = c1 - 1 + PT;
+  const int tl = min(te, nt - 1);
+#pragma unroll
+  for (int sidx = 0; sidx < D - 1; ++sidx) issue(tb + sidx, (tb + sidx) % D);
+  for (int t = tb; t <= te; ++t) {
+    wait_vmcnt<(D - 2) * K>();
+    __syncthreads();
+    issue(t + D - 1, (t + D - 1) % D);  // always K copies (clamped slices past the end)
+    const double* buf = sm + (t % D) * slot;
+    if (t <= tl) {  // uniform
+      double x1 = 0.0, x2 = 0.0, x3 = 0.0;
+#pragma unroll
+      for (int o = 0; o < BW; ++o) {
+        const int rr = drc + o;
+        const double a = buf[rr * LB + li];
+        const double b = buf[arr + rr * LB + li];
+        const double c = buf[2 * arr + rr * LB + li];
+        x1 += cm[o] * a;
+        x2 += cj[o] * a + cm[o] * b + 2.0 * ck[o] * c;
+        x3 += ck[o] * a + cm[o] * c;
+      }
+      const double s1 = x1, s2 = k2 * x2;
+      if (t == nt - 1) s3 = kw * x3;
+      const double* kt = Kt + t * W;
+      const double* mt = Mt + t * W;
+#pragma unroll
+      for (int k = 0; k < W; ++k) acc[k] += kt[k] * s1 + mt[k] * s2;
+    }
+    const int to = t - PT;
+    if (to >= c0) {  // uniform
+      double v = acc[0];
+      if (to == nt - 1) v += s3;
+      if (DOT) dsum += mine ? v * buf[3 * arr + drc * LB + li] : 0.0;
+      if (mine) y[(size_t)to * plane + (size_t)rowc * L + lc] = v;
+    }
+#pragma unroll
+    for (int k = 0; k < W - 1; ++k) acc[k] = acc[k + 1];
+    acc[W - 1] = 0.0;
+  }
+  if constexpr (DOT) {
+    const double sblk = block_sum(dsum, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = sblk;
+  }
+}
+
+// Launch the slab inner stage when the slab fits (n1, n2 <= 64, equal
+// degrees in directions 1 and 2).  Returns 1 when the shape is not covered
+// (nothing launched); otherwise 0, with the launch status in *err.
+static int launch_inner_slab(stls_ctx* h, const double* x, hipError_t* err) {
+  const DevDir& D1 = h->dd[0];
+  const DevDir& D2 = h->dd[1];
+  const int n1 = D1.n, n2 = D2.n;
+  if (n1 > 64 || n2 > 64 || D1.p != D2.p) return 1;
+  const int ld = n1 | 1;
+  const size_t shmem = sizeof(double) * ((size_t)n1 * n2 + 3 * (size_t)n2 * ld);
+  if (shmem > 160 * 1024) return 1;
+  void (*kern)(const double*, double*, double*, double*, int, int, int, int, const double*, const double*,
+               const double*, const double*, const double*, const double*) = nullptr;
+  switch (D1.p) {
+    case 1: kern = mv_inner_slab_kernel<1>; break;
+    case 2: kern = mv_inner_slab_kernel<2>; break;
+    case 3: kern = mv_inner_slab_kernel<3>; break;
+    case 4: kern = mv_inner_slab_kernel<4>; break;
+    case 5: kern = mv_inner_slab_kernel<5>; break;
+    case 6: kern = mv_inner_slab_kernel<6>; break;
+    default: return 1;
+  }
+  *err = hipSuccess;
+  if (shmem > 65536) {
+    *err = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (*err != hipSuccess) return 0;
+  }
+  const int nslab = (int)(h->ndof / ((int64_t)n1 * n2));
+  double** w = h->work;
+  prof_begin(h);
+  hipLaunchKernelGGL(kern, dim3(nslab), dim3(kSlabWaves * 64), shmem, h->stream, x, w[0], w[1], w[2], n1, n2, nslab,
+                     ld, D1.M, D1.J, D1.K, D2.M, D2.J, D2.K);
+  *err = hipGetLastError();
+  prof_end(h, PROF_MV_INNER2);
+  return 0;
+}
+
+// Launch the DMA-pipelined outer stage when it covers the shape (L even and
+// >= 16, equal space and time degrees <= 6).  Returns 1 when not covered,
+// 0 when launched, < 0 on error.
+static int launch_outer_dma(stls_ctx* h, const double* A, const double* B, const double* C, double* y, int L,
+                            const double* dot_with, double* partials, int* nparts) {
+  const int d = h->d;
+  const DevDir& Dd = h->dd[d - 1];
+  const DevDir& Dt = h->dd[d];
+  const int nd = Dd.n, nt = Dt.n, P = Dd.p;
+  if (L % 2 != 0 || L < kDmaLb || P != Dt.p || P < 1 || P > 6) return 1;
+  const int ntd = (nd + 15) / 16;
+  const int Td = (nd + ntd - 1) / ntd;
+  const int rows = Td + 2 * P;
+  const int rb8 = (rows + 7) / 8;
+  const int rbd = dot_with ? (Td + 7) / 8 : 0;
+  const int K = std::max(2, (3 * rb8 + rbd + 3) / 4);
+  if (K > 4) return 1;
+  const int nlb = (L + kDmaLb - 1) / kDmaLb;
+  int nchunk = 1;
+  while (nlb * ntd * nchunk < 512 && (nt + nchunk) / (nchunk + 1) >= std::max(4 * P, 8)) ++nchunk;
+  const int Tc = (nt + nchunk - 1) / nchunk;
+  nchunk = (nt + Tc - 1) / Tc;
+  const int blocks = nlb * ntd * nchunk;
+  if (dot_with && blocks > kPartialsCap) return 1;
+  if (nparts) *nparts = blocks;
+  const size_t shmem = sizeof(double) * kDmaSlots * ((size_t)(3 * rb8 + rbd) * 8 * kDmaLb + 8 * kDmaLb);
+  void (*kern)(const double*, const double*, const double*, double*, int, int, int, int, int, int, int, int,
+               const double*, const double*, const double*, const double*, const double*, double, double,
+               const double*, double*) = nullptr;
+  const bool dot = dot_with != nullptr;
+#define STLS_DMA_K(PV, KV)                                                                              \
+  if (K == KV) kern = dot ? mv_outer_dma_kernel<PV, PV, KV, true> : mv_outer_dma_kernel<PV, PV, KV, false>;
+#define STLS_DMA_P(PV) \
+  case PV: STLS_DMA_K(PV, 2) STLS_DMA_K(PV, 3) STLS_DMA_K(PV, 4) break;
+  switch (P) {
+    STLS_DMA_P(1) STLS_DMA_P(2) STLS_DMA_P(3) STLS_DMA_P(4) STLS_DMA_P(5) STLS_DMA_P(6)
+    default: return 1;
+  }
+#undef STLS_DMA_K
+#undef STLS_DMA_P
+  if (!kern) return 1;
+  hipError_t e;
+  if (shmem > 65536) {
+    e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(LDS)");
+  }
+  const double k2 = h->kappa * h->kappa, kw = h->kappa * h->dir[d].wend;
+  prof_begin(h);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), shmem, h->stream, A, B, C, y, L, nd, nt, Td, nlb, ntd, nchunk,
+                     Tc, Dd.M, Dd.J, Dd.K, Dt.K, Dt.M, k2, kw, dot_with, partials);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "mv_outer_dma_kernel launch");
+  prof_end(h, PROF_MV_OUTER);
+  return 0;
+}
+
 int launch_matvec(stls_ctx* h, const double* x, double* y, const double* dot_with, double* partials,
                   int* nparts) {
   const int d = h->d;
@@ -1043,6 +1400,10 @@ int launch_matvec(stls_ctx* h, const double* x, double* y, const double* dot_wit
     prof_end(h, PROF_MV_INNER1);
     A = w[0]; B = w[1]; C = w[2];
     L = D1.n;
+  } else if (d == 3 && launch_inner_slab(h, x, &e) == 0) {
+    if (e != hipSuccess) return hip_fail(e, "mv_inner_slab_kernel launch");
+    A = w[0]; B = w[1]; C = w[2];
+    L = h->dd[0].n * h->dd[1].n;
   } else if (d == 3) {
     const DevDir& D1 = h->dd[0];
     const DevDir& D2 = h->dd[1];
@@ -1082,6 +1443,10 @@ int launch_matvec(stls_ctx* h, const double* x, double* y, const double* dot_wit
     prof_end(h, PROF_MV_INNER2);
     A = w[0]; B = w[1]; C = w[2];
     L = n1 * n2;
+  }
+  if (B != nullptr) {
+    const int st = launch_outer_dma(h, A, B, C, y, L, dot_with, partials, nparts);
+    if (st <= 0) return st;  // launched (0) or failed (< 0); > 0: shape not covered
   }
   const DevDir& Dd = h->dd[d - 1];
   const DevDir& Dt = h->dd[d];
