@@ -1,0 +1,400 @@
+// BF16x3 fast-diagonalization chain for three space dimensions (§4.3,
+// Algorithm 1 steps 2-4) in five passes:
+//   1. slab pass, forward:  modes 1 and 2 of every (i3, t) slab, r (FP64) -> FP32
+//   2. strided pass:        mode 3 forward
+//   3. strided fused pass:  time mode forward, division by the eigenvalue sum
+//                           (FP64), time mode backward
+//   4. strided pass:        mode 3 backward
+//   5. slab pass, backward: modes 2 and 1, FP32 -> s (FP64), partial sums of s . r
+// Every product W X is formed as W_hi X_hi + W_hi X_lo + W_lo X_hi on MFMA
+// bf16 16x16x32 with FP32 accumulation; operands are FP32 values split into
+// bf16 hi + lo halves by hardware round-to-nearest-even conversions.
+// Fragment layout of v_mfma_f32_16x16x32_bf16 (lane l, e = 0..7, r = 0..3):
+//   A(i = l%16, k = 8(l/16) + e), B(k = 8(l/16) + e, j = l%16),
+//   D(4(l/16) + r, l%16).
+// The operator fragments (row-major [i*kpad + k] bf16 halves of W = U^T or
+// W = U) stay in registers for the whole kernel; workgroups are persistent.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "stls_internal.h"
+
+namespace stls {
+namespace {
+
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ inline void split8(const float* v, bf8_t& h, bf8_t& l) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 a = (__bf16)v[e];
+    h[e] = a;
+    l[e] = (__bf16)(v[e] - (float)a);
+  }
+}
+__device__ inline bf8_t ld8(const void* p) { return *reinterpret_cast<const bf8_t*>(p); }
+__device__ inline f4v mfma3(bf8_t ah, bf8_t al, bf8_t bh, bf8_t bl, f4v c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// Slab pass: for each slab X (n2 x n1, i1 fastest) computes
+//   Y = X W1^T (mode 1),  Z = W2 Y (mode 2)
+// with n1, n2 <= 16 NM (both directions padded to 16 NM rows, n1 even).
+// Wave w owns rows i2 in [16w, 16w+16) of the mode-1 product, its A
+// fragments read straight from global memory, and rows j2 in [16w, 16w+16)
+// of the mode-2 product.  Y crosses waves through a double-buffered LDS tile
+// [j1][i2] of bf16 halves (one barrier per slab).  The next slab of X is
+// fetched into registers while the current one is processed.
+constexpr int kSlabLdy = 72;  // bf16 row stride of the Y tile (64 + 8)
+
+template <int NM, typename TI, typename TO, bool DOT>
+__global__ __launch_bounds__(256) void fd_slab_bf16_kernel(const TI* __restrict__ X, TO* __restrict__ Z, int n1,
+                                                           int n2, int nslab, const __bf16* __restrict__ W1h,
+                                                           const __bf16* __restrict__ W1l,
+                                                           const __bf16* __restrict__ W2h,
+                                                           const __bf16* __restrict__ W2l,
+                                                           const double* __restrict__ dotv,
+                                                           double* __restrict__ partials) {
+  constexpr int NK = (NM + 1) / 2;
+  constexpr int KPAD = NK * 32;
+  constexpr int NP = NM * 16;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __bf16* ytile = reinterpret_cast<__bf16*>(smem_raw);  // 2 buffers x {hi, lo} x [64][kSlabLdy]
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, cl = lane & 15;
+  bf8_t b1h[NM][NK], b1l[NM][NK], a2h[NK], a2l[NK];
+#pragma unroll
+  for (int kb = 0; kb < NK; ++kb) {
+#pragma unroll
+    for (int nt = 0; nt < NM; ++nt) {
+      const int off = (16 * nt + cl) * KPAD + 32 * kb + 8 * g;
+      b1h[nt][kb] = ld8(W1h + off);
+      b1l[nt][kb] = ld8(W1l + off);
+    }
+    const int off2 = min(16 * wave + cl, NP - 1) * KPAD + 32 * kb + 8 * g;
+    a2h[kb] = ld8(W2h + off2);
+    a2l[kb] = ld8(W2l + off2);
+  }
+  const int ns = n1 * n2;
+  const int i2 = min(16 * wave + cl, n2 - 1);  // A-fragment row of this lane (rows >= n2 masked below)
+  TI px[NK][8];
+  auto fetch = [&](int sl) {
+    const TI* row = X + (size_t)sl * ns + (size_t)i2 * n1;
+#pragma unroll
+    for (int kb = 0; kb < NK; ++kb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c0 = 32 * kb + 8 * g + 2 * q;  // n1 even: pairs never straddle a row
+        const bool ok = c0 < n1;
+        if constexpr (sizeof(TI) == 8) {
+          const double2 w = *reinterpret_cast<const double2*>(row + (ok ? c0 : 0));
+          px[kb][2 * q] = ok ? w.x : 0.0;
+          px[kb][2 * q + 1] = ok ? w.y : 0.0;
+        } else {
+          const float2 w = *reinterpret_cast<const float2*>(row + (ok ? c0 : 0));
+          px[kb][2 * q] = ok ? w.x : 0.f;
+          px[kb][2 * q + 1] = ok ? w.y : 0.f;
+        }
+      }
+  };
+  const int j2o = 16 * wave + 4 * g;  // output rows j2o + r of this lane
+  double dsum = 0.0;
+  const int s0 = blockIdx.x;
+  if (s0 < nslab) fetch(s0);
+  int buf = 0;
+  for (int sl = s0; sl < nslab; sl += gridDim.x) {
+    double dv[DOT ? NM * 4 : 1];
+    const size_t base = (size_t)sl * ns;
+    if constexpr (DOT) {
+#pragma unroll
+      for (int nt = 0; nt < NM; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          dv[nt * 4 + r] = dotv[base + (size_t)min(j2o + r, n2 - 1) * n1 + min(16 * nt + cl, n1 - 1)];
+    }
+    bf8_t xh[NK], xl[NK];
+#pragma unroll
+    for (int kb = 0; kb < NK; ++kb) {
+      float v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (float)px[kb][e];
+      split8(v, xh[kb], xl[kb]);
+    }
+    fetch(min(sl + (int)gridDim.x, nslab - 1));  // always issued: uniform load order
+    __bf16* yh = ytile + buf * 2 * 64 * kSlabLdy;
+    __bf16* yl = yh + 64 * kSlabLdy;
+#pragma unroll
+    for (int nt = 0; nt < NM; ++nt) {
+      f4v acc = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < NK; ++kb) acc = mfma3(xh[kb], xl[kb], b1h[nt][kb], b1l[nt][kb], acc);
+      // the lane holds Y(16w + 4g + r, 16nt + cl); rows past n2 are zeroed
+      bf4_t hh, ll;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float yv = (j2o + r < n2) ? acc[r] : 0.f;
+        const __bf16 a = (__bf16)yv;
+        hh[r] = a;
+        ll[r] = (__bf16)(yv - (float)a);
+      }
+      const int o = (16 * nt + cl) * kSlabLdy + j2o;
+      *reinterpret_cast<bf4_t*>(yh + o) = hh;
+      *reinterpret_cast<bf4_t*>(yl + o) = ll;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int nt = 0; nt < NM; ++nt) {
+      f4v acc = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < NK; ++kb) {
+        const int o = (16 * nt + cl) * kSlabLdy + 32 * kb + 8 * g;
+        acc = mfma3(a2h[kb], a2l[kb], ld8(yh + o), ld8(yl + o), acc);
+      }
+      const int j1 = 16 * nt + cl;
+      if (j1 < n1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (j2o + r < n2) {
+            const TO zv = (TO)acc[r];
+            if constexpr (DOT) dsum += (double)zv * dv[nt * 4 + r];
+            Z[base + (size_t)(j2o + r) * n1 + j1] = zv;
+          }
+        }
+      }
+    }
+    buf ^= 1;
+  }
+  if constexpr (DOT) {
+    for (int off = 32; off > 0; off >>= 1) dsum += __shfl_xor(dsum, off, 64);
+    if (lane == 0) red[wave] = dsum;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Strided pass over the (L, n, R) view (n <= 16 NM): Y(i, c) = sum_k W(i, k) X(k, c).
+// One wave handles 16 consecutive columns at a time, its B fragments loaded
+// straight from global memory (8 consecutive k of one column per lane), two
+// such units prefetched into registers (two register sets, unrolled, so that
+// no copy of an in-flight value forces an early wait).  FUSED: time mode,
+//   Q(i, c) = (W X)(i, c) / (lambda_t[i] + lambda_s[c])  (FP64 division),
+//   Y = W2 Q,
+// with Q re-fragmented through a per-wave LDS scratch tile.
+constexpr int kStridedWaves = 8;
+constexpr int kStridedDepth = 2;
+
+template <int NM, bool FUSED>
+__global__ __launch_bounds__(kStridedWaves * 64) void fd_strided_bf16_kernel(
+    const float* __restrict__ X, float* __restrict__ Y, int L, int n, int ncols, const __bf16* __restrict__ Wh,
+    const __bf16* __restrict__ Wl, const __bf16* __restrict__ W2h, const __bf16* __restrict__ W2l,
+    const double* __restrict__ lam_t, const double* __restrict__ lam_s) {
+  constexpr int NK = (NM + 1) / 2;
+  constexpr int KPAD = NK * 32;
+  constexpr int LDS_S = KPAD + 4;
+  constexpr int DEPTH = kStridedDepth;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, cl = lane & 15;
+  float* myscr = reinterpret_cast<float*>(smem_raw) + wave * 16 * LDS_S;
+  bf8_t wh[NM][NK], wl[NM][NK];
+  bf8_t vh[FUSED ? NM : 1][NK], vl[FUSED ? NM : 1][NK];
+#pragma unroll
+  for (int t = 0; t < NM; ++t)
+#pragma unroll
+    for (int kb = 0; kb < NK; ++kb) {
+      const int off = (16 * t + cl) * KPAD + 32 * kb + 8 * g;
+      wh[t][kb] = ld8(Wh + off);
+      wl[t][kb] = ld8(Wl + off);
+      if constexpr (FUSED) {
+        vh[t][kb] = ld8(W2h + off);
+        vl[t][kb] = ld8(W2l + off);
+      }
+    }
+  const int nunits = (ncols + 15) / 16;
+  const int Ln = L * n;
+  auto base_of = [&](int c) -> int { return (c % L) + (c / L) * Ln; };
+  float pv[DEPTH][NK][8];
+  auto fetch = [&](int u, float (&v)[NK][8]) {
+    const int b = base_of(min(u * 16 + cl, ncols - 1));
+#pragma unroll
+    for (int kb = 0; kb < NK; ++kb)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 32 * kb + 8 * g + e;
+        const float x = X[b + min(k, n - 1) * L];
+        v[kb][e] = k < n ? x : 0.f;
+      }
+  };
+  const int stride = gridDim.x * kStridedWaves;
+  const int u0 = blockIdx.x * kStridedWaves + wave;
+  if (u0 >= nunits) return;
+#pragma unroll
+  for (int d = 0; d < DEPTH; ++d) fetch(min(u0 + d * stride, nunits - 1), pv[d]);
+  for (int ub = u0; ub < nunits; ub += DEPTH * stride) {
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) {
+      const int u = ub + d * stride;
+      const int c = min(u, nunits - 1) * 16 + cl;
+      bf8_t xh[NK], xl[NK];
+#pragma unroll
+      for (int kb = 0; kb < NK; ++kb) split8(pv[d][kb], xh[kb], xl[kb]);
+      fetch(min(u + DEPTH * stride, nunits - 1), pv[d]);  // always issued: uniform load order
+      f4v acc[NM];
+#pragma unroll
+      for (int t = 0; t < NM; ++t) {
+        acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < NK; ++kb) acc[t] = mfma3(wh[t][kb], wl[t][kb], xh[kb], xl[kb], acc[t]);
+      }
+      if constexpr (FUSED) {
+        const double ls = lam_s[min(c, ncols - 1)];
+#pragma unroll
+        for (int t = 0; t < NM; ++t) {
+          f4v q;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * t + 4 * g + r;
+            q[r] = i < n ? (float)((double)acc[t][r] / (lam_t[min(i, n - 1)] + ls)) : 0.f;
+          }
+          *reinterpret_cast<f4v*>(myscr + cl * LDS_S + 16 * t + 4 * g) = q;
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int kb = 0; kb < NK; ++kb) {
+          float v[8];
+          const f4v a = *reinterpret_cast<const f4v*>(myscr + cl * LDS_S + 32 * kb + 8 * g);
+          const f4v b = *reinterpret_cast<const f4v*>(myscr + cl * LDS_S + 32 * kb + 8 * g + 4);
+          // rows past n (including the k padding the tile never holds) are zero
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            v[e] = 32 * kb + 8 * g + e < n ? a[e] : 0.f;
+            v[4 + e] = 32 * kb + 8 * g + 4 + e < n ? b[e] : 0.f;
+          }
+          split8(v, xh[kb], xl[kb]);
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int t = 0; t < NM; ++t) {
+          acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int kb = 0; kb < NK; ++kb) acc[t] = mfma3(vh[t][kb], vl[t][kb], xh[kb], xl[kb], acc[t]);
+        }
+      }
+      if (u < nunits && c < ncols) {
+        const int b = base_of(c);
+#pragma unroll
+        for (int t = 0; t < NM; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * t + 4 * g + r;
+            if (i < n) Y[b + i * L] = acc[t][r];
+          }
+      }
+    }
+  }
+}
+
+template <int NM, typename TI, typename TO, bool DOT>
+int launch_slab(stls_ctx* h, const TI* X, TO* Z, bool fwd, const double* dotv, double* partials, int* nparts) {
+  const DevDir& D1 = h->dd[0];
+  const DevDir& D2 = h->dd[1];
+  const int n1 = D1.n, n2 = D2.n;
+  const int nslab = (int)(h->ndof / ((int64_t)n1 * n2));
+  const int blocks = std::min(nslab, 2 * 256);
+  if (nparts) *nparts = blocks;
+  const size_t shmem = sizeof(__bf16) * 2 * 2 * 64 * kSlabLdy;
+  const __bf16* W1h = (const __bf16*)(fwd ? D1.Hfwd : D1.Hbwd);
+  const __bf16* W1l = (const __bf16*)(fwd ? D1.Lfwd : D1.Lbwd);
+  const __bf16* W2h = (const __bf16*)(fwd ? D2.Hfwd : D2.Hbwd);
+  const __bf16* W2l = (const __bf16*)(fwd ? D2.Lfwd : D2.Lbwd);
+  prof_begin(h);
+  hipLaunchKernelGGL((fd_slab_bf16_kernel<NM, TI, TO, DOT>), dim3(blocks), dim3(256), shmem, h->stream, X, Z, n1, n2,
+                     nslab, W1h, W1l, W2h, W2l, dotv, partials);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "fd_slab_bf16_kernel launch");
+  prof_end(h, PROF_FD_SPACE);
+  return STLS_OK;
+}
+
+template <int NM, bool FUSED>
+int launch_strided(stls_ctx* h, const float* X, float* Y, int L, int k, bool fwd, const double* lam_t) {
+  const DevDir& D = h->dd[k];
+  const int n = D.n;
+  const int ncols = (int)(h->ndof / n);
+  const int nunits = (ncols + 15) / 16;
+  const int blocks = std::max(1, std::min((nunits + kStridedWaves - 1) / kStridedWaves, 256));
+  constexpr int NK = (NM + 1) / 2;
+  const size_t shmem = FUSED ? sizeof(float) * kStridedWaves * 16 * (NK * 32 + 4) : 0;
+  const __bf16* Wh = (const __bf16*)(fwd ? D.Hfwd : D.Hbwd);
+  const __bf16* Wl = (const __bf16*)(fwd ? D.Lfwd : D.Lbwd);
+  const __bf16* W2h = FUSED ? (const __bf16*)D.Hbwd : nullptr;
+  const __bf16* W2l = FUSED ? (const __bf16*)D.Lbwd : nullptr;
+  prof_begin(h);
+  hipLaunchKernelGGL((fd_strided_bf16_kernel<NM, FUSED>), dim3(blocks), dim3(kStridedWaves * 64), shmem, h->stream, X,
+                     Y, L, n, ncols, Wh, Wl, W2h, W2l, lam_t, h->lam_s);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "fd_strided_bf16_kernel launch");
+  prof_end(h, FUSED ? PROF_FD_TIME : PROF_FD_SPACE);
+  return STLS_OK;
+}
+
+template <bool FUSED>
+int strided_nm(stls_ctx* h, const float* X, float* Y, int L, int k, bool fwd, const double* lam_t) {
+  switch (h->dd[k].npad / 16) {
+    case 1: return launch_strided<1, FUSED>(h, X, Y, L, k, fwd, lam_t);
+    case 2: return launch_strided<2, FUSED>(h, X, Y, L, k, fwd, lam_t);
+    case 3: return launch_strided<3, FUSED>(h, X, Y, L, k, fwd, lam_t);
+    case 4: return launch_strided<4, FUSED>(h, X, Y, L, k, fwd, lam_t);
+    default: set_error("direction too large for the strided bf16 pass"); return STLS_EINVAL;
+  }
+}
+
+template <typename TI, typename TO, bool DOT>
+int slab_nm(stls_ctx* h, const TI* X, TO* Z, bool fwd, const double* dotv, double* partials, int* nparts) {
+  switch (h->dd[0].npad / 16) {
+    case 1: return launch_slab<1, TI, TO, DOT>(h, X, Z, fwd, dotv, partials, nparts);
+    case 2: return launch_slab<2, TI, TO, DOT>(h, X, Z, fwd, dotv, partials, nparts);
+    case 3: return launch_slab<3, TI, TO, DOT>(h, X, Z, fwd, dotv, partials, nparts);
+    case 4: return launch_slab<4, TI, TO, DOT>(h, X, Z, fwd, dotv, partials, nparts);
+    default: set_error("direction too large for the slab bf16 pass"); return STLS_EINVAL;
+  }
+}
+
+}  // namespace
+
+// Shapes covered: d = 3, every restricted size <= 64, n1 even, directions 1
+// and 2 padded alike, L = n1 n2 n3 and n1 n2 products fitting 32-bit offsets.
+bool fd_bf16_five_pass_covers(const stls_ctx* h) {
+  if (h->d != 3) return false;
+  for (int k = 0; k <= 3; ++k)
+    if (h->dir[k].n > 64) return false;
+  if (h->dir[0].n % 2 != 0 || h->dd[0].npad != h->dd[1].npad) return false;
+  return h->ndof < ((int64_t)1 << 31);
+}
+
+int prec_apply_bf16x3_five_pass(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
+                                int* nparts) {
+  float* b0 = reinterpret_cast<float*>(h->fdbuf[0]);
+  float* b1 = reinterpret_cast<float*>(h->fdbuf[1]);
+  const int n1 = h->dir[0].n, n2 = h->dir[1].n;
+  const int L3 = n1 * n2;
+  const int ns = (int)h->ns;
+  int st;
+  if ((st = slab_nm<double, float, false>(h, r, b0, true, nullptr, nullptr, nullptr))) return st;
+  if ((st = strided_nm<false>(h, b0, b1, L3, 2, true, nullptr))) return st;
+  if ((st = strided_nm<true>(h, b1, b0, ns, 3, true, h->dd[3].lam))) return st;
+  if ((st = strided_nm<false>(h, b0, b1, L3, 2, false, nullptr))) return st;
+  if (dot_with) return slab_nm<float, double, true>(h, b1, s, false, dot_with, partials, nparts);
+  return slab_nm<float, double, false>(h, b1, s, false, nullptr, nullptr, nparts);
+}
+
+}  // namespace stls

@@ -139,6 +139,10 @@ int launch_matvec(stls_ctx* h, const double* x, double* y, const double* dot_wit
 int pcg_run(stls_ctx* h, const double* b, double* x, double rtol, int maxit, int* iters,
             double* relres);
 int upload_fd_operands(stls_ctx* h, int k);
+// Five-pass BF16x3 FD chain for d = 3 (stls_fd.hip).
+bool fd_bf16_five_pass_covers(const stls_ctx* h);
+int prec_apply_bf16x3_five_pass(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
+                                int* nparts);
 int ensure_diff_operands(stls_ctx* h);
 
 // profiling helpers

@@ -660,7 +660,9 @@ int launch_prec_apply(stls_ctx* h, const double* r, double* s, const double* dot
   switch (h->fd_mode) {
     case STLS_FD_FP64: return prec_apply_t<double>(h, r, s, dot_with, partials, nparts);
     case STLS_FD_FP32: return prec_apply_t<float>(h, r, s, dot_with, partials, nparts);
-    case STLS_FD_BF16X3: return prec_apply_bf16x3(h, r, s, dot_with, partials, nparts);
+    case STLS_FD_BF16X3:
+      if (fd_bf16_five_pass_covers(h)) return prec_apply_bf16x3_five_pass(h, r, s, dot_with, partials, nparts);
+      return prec_apply_bf16x3(h, r, s, dot_with, partials, nparts);
     default: set_error("FD precision mode not available"); return STLS_EINVAL;
   }
 }
