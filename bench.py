@@ -34,21 +34,36 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_algorithmic(cls, d, n, N, ns, fd_bytes):
-    """(flops, bytes) per launch of each kernel class (algorithmic counts:
-    dense products without padding, each stream read or written once)."""
-    nt = n[d]
+def kernel_bytes(cls, mode, five_pass, N):
+    """Algorithmic HBM bytes per launch of a profiling class (each stream read
+    or written once, FP64 PCG vectors, FP32 FD intermediates unless FP64)."""
+    if cls == "fd_slab":  # slab forward r -> FP32 (12 B/dof), backward FP32 -> s plus the dot with r (20 B/dof)
+        return 16.0 * N
     if cls == "fd_space":
-        nbar = sum(n[:d]) / d
-        return 2.0 * nbar * N, fd_bytes * N
+        if five_pass:  # FP32 -> FP32 single-mode passes
+            return 8.0 * N
+        sb = 8.0 if mode == "fp64" else 4.0  # six passes: first reads r, last writes s and reads r for the dot
+        return (24.0 + 10.0 * sb) / 6.0 * N
     if cls == "fd_time":
-        return 4.0 * nt * N, fd_bytes * N
-    streams = {"mv_inner1": 4, "mv_inner2": 6, "mv_space": 5 if d > 1 else 3, "mv_time": 4}
-    if cls in streams:
-        return None, 8.0 * streams[cls] * N
-    if cls == "mv_last":
-        return None, 8.0 * 3 * ns
-    return None, None
+        return 8.0 * N if five_pass else (16.0 if mode == "fp64" else 8.0) * N
+    return {"mv_inner2": 32.0 * N,   # x in, A, B, C out
+            "mv_outer": 40.0 * N,    # A, B, C and the dot operand in, y out
+            "vec": 36.0 * N}.get(cls)  # mean of x,r update (48 B/dof) and p update (24 B/dof)
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of ``cls`` from the committed counter summary, if
+    it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    from paper_1809_10026_amd.profile_summary import source_hash
+    with open(path) as f:
+        data = json.load(f)
+    if data.get("source_sha256") != source_hash() or cls not in data.get("classes", {}):
+        return None
+    c = data["classes"][cls]
+    return c["fetch_bytes"] + c["write_bytes"]
 
 
 def main():
@@ -149,28 +164,26 @@ def main():
 
     # roofline of the dominant kernel class of the headline (timed) solves
     prof = res[mixed]["prof"]
+    five_pass = prof.get("fd_slab", (0, 0.0))[0] > 0
     classes = []
     for cls, (launches, ms) in prof.items():
         if launches == 0:
             continue
-        flops, byts = kernel_algorithmic(cls, d, shape, N, ns, fd_bytes=8.0 if mixed == "fp64" else 8.0)
         avg_s = ms / launches / 1e3
         entry = dict(kernel=cls, launches=launches, total_ms=ms, avg_us=avg_s * 1e6)
-        if cls.startswith("fd_") and mixed == "fp32":
-            entry.update(bound="mfma", achieved=flops / avg_s / 1e12, peak=PEAK["fp32_TF"], unit="TFLOP/s")
-        elif cls.startswith("fd_"):
-            # bf16x3: three bf16 products per FP32 product; HBM-bound at FP32 intermediates
-            entry.update(bound="hbm", achieved=byts / avg_s / 1e9, peak=PEAK["hbm_GBs"], unit="GB/s",
-                         mfma_bf16_TFs=3 * flops / avg_s / 1e12)
-        elif byts is not None:
-            entry.update(bound="hbm", achieved=byts / avg_s / 1e9, peak=PEAK["hbm_GBs"], unit="GB/s")
-        if "achieved" in entry:
+        byts = kernel_bytes(cls, mixed, five_pass, N)
+        if byts is not None:
+            entry.update(bound="hbm", bytes_per_launch=byts, achieved=byts / avg_s / 1e9, peak=PEAK["hbm_GBs"],
+                         unit="GB/s")
             entry["frac"] = entry["achieved"] / entry["peak"]
         classes.append(entry)
     classes.sort(key=lambda e: -e["total_ms"])
     dom = next(e for e in classes if "achieved" in e)
+    traffic = measured_traffic(dom["kernel"])
     roofline = dict(kernel=dom["kernel"], bound=dom["bound"], achieved=round(dom["achieved"], 3),
-                    peak=dom["peak"], unit=dom["unit"], frac=round(dom["frac"], 4), traffic=None,
+                    peak=dom["peak"], unit=dom["unit"], frac=round(dom["frac"], 4),
+                    traffic=None if traffic is None else round(traffic / 1e6, 3),
+                    traffic_unit="MB per launch", algorithmic_MB_per_launch=round(dom["bytes_per_launch"] / 1e6, 3),
                     avg_us=round(dom["avg_us"], 3))
 
     cpu = None

@@ -3,7 +3,7 @@
 //   1. slab pass, forward:  modes 1 and 2 of every (i3, t) slab, r (FP64) -> FP32
 //   2. strided pass:        mode 3 forward
 //   3. strided fused pass:  time mode forward, division by the eigenvalue sum
-//                           (FP64), time mode backward
+//                           (FP64 sum, FP32 quotient), time mode backward
 //   4. strided pass:        mode 3 backward
 //   5. slab pass, backward: modes 2 and 1, FP32 -> s (FP64), partial sums of s . r
 // Every product W X is formed as W_hi X_hi + W_hi X_lo + W_lo X_hi on MFMA
@@ -61,7 +61,9 @@ __global__ __launch_bounds__(256) void fd_slab_bf16_kernel(const TI* __restrict_
                                                            const __bf16* __restrict__ W2h,
                                                            const __bf16* __restrict__ W2l,
                                                            const double* __restrict__ dotv,
-                                                           double* __restrict__ partials) {
+                                                           double* __restrict__ partials,
+                                                           const PcgScalars* __restrict__ gate) {
+  if (gate && (gate->done | gate->flag)) return;  // PCG already finished: nothing to do
   constexpr int NK = (NM + 1) / 2;
   constexpr int KPAD = NK * 32;
   constexpr int NP = NM * 16;
@@ -186,7 +188,7 @@ __global__ __launch_bounds__(256) void fd_slab_bf16_kernel(const TI* __restrict_
 // straight from global memory (8 consecutive k of one column per lane), two
 // such units prefetched into registers (two register sets, unrolled, so that
 // no copy of an in-flight value forces an early wait).  FUSED: time mode,
-//   Q(i, c) = (W X)(i, c) / (lambda_t[i] + lambda_s[c])  (FP64 division),
+//   Q(i, c) = (W X)(i, c) / (lambda_t[i] + lambda_s[c])  (FP32 quotient),
 //   Y = W2 Q,
 // with Q re-fragmented through a per-wave LDS scratch tile.
 constexpr int kStridedWaves = 8;
@@ -196,7 +198,8 @@ template <int NM, bool FUSED>
 __global__ __launch_bounds__(kStridedWaves * 64) void fd_strided_bf16_kernel(
     const float* __restrict__ X, float* __restrict__ Y, int L, int n, int ncols, const __bf16* __restrict__ Wh,
     const __bf16* __restrict__ Wl, const __bf16* __restrict__ W2h, const __bf16* __restrict__ W2l,
-    const double* __restrict__ lam_t, const double* __restrict__ lam_s) {
+    const double* __restrict__ lam_t, const double* __restrict__ lam_s, const PcgScalars* __restrict__ gate) {
+  if (gate && (gate->done | gate->flag)) return;  // PCG already finished: nothing to do
   constexpr int NK = (NM + 1) / 2;
   constexpr int KPAD = NK * 32;
   constexpr int LDS_S = KPAD + 4;
@@ -262,8 +265,11 @@ __global__ __launch_bounds__(kStridedWaves * 64) void fd_strided_bf16_kernel(
           f4v q;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
+            // the quotient is rounded to FP32 at once: an FP32 reciprocal of
+            // the FP64 eigenvalue sum loses nothing the bf16x3 products keep
             const int i = 16 * t + 4 * g + r;
-            q[r] = i < n ? (float)((double)acc[t][r] / (lam_t[min(i, n - 1)] + ls)) : 0.f;
+            const float den = (float)(lam_t[min(i, n - 1)] + ls);
+            q[r] = i < n ? acc[t][r] * __builtin_amdgcn_rcpf(den) : 0.f;
           }
           *reinterpret_cast<f4v*>(myscr + cl * LDS_S + 16 * t + 4 * g) = q;
         }
@@ -318,10 +324,10 @@ int launch_slab(stls_ctx* h, const TI* X, TO* Z, bool fwd, const double* dotv, d
   const __bf16* W2l = (const __bf16*)(fwd ? D2.Lfwd : D2.Lbwd);
   prof_begin(h);
   hipLaunchKernelGGL((fd_slab_bf16_kernel<NM, TI, TO, DOT>), dim3(blocks), dim3(256), shmem, h->stream, X, Z, n1, n2,
-                     nslab, W1h, W1l, W2h, W2l, dotv, partials);
+                     nslab, W1h, W1l, W2h, W2l, dotv, partials, h->gate);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "fd_slab_bf16_kernel launch");
-  prof_end(h, PROF_FD_SPACE);
+  prof_end(h, PROF_FD_SLAB);
   return STLS_OK;
 }
 
@@ -340,7 +346,7 @@ int launch_strided(stls_ctx* h, const float* X, float* Y, int L, int k, bool fwd
   const __bf16* W2l = FUSED ? (const __bf16*)D.Lbwd : nullptr;
   prof_begin(h);
   hipLaunchKernelGGL((fd_strided_bf16_kernel<NM, FUSED>), dim3(blocks), dim3(kStridedWaves * 64), shmem, h->stream, X,
-                     Y, L, n, ncols, Wh, Wl, W2h, W2l, lam_t, h->lam_s);
+                     Y, L, n, ncols, Wh, Wl, W2h, W2l, lam_t, h->lam_s, h->gate);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "fd_strided_bf16_kernel launch");
   prof_end(h, FUSED ? PROF_FD_TIME : PROF_FD_SPACE);

@@ -468,6 +468,8 @@ static void free_ctx(stls_ctx* h) {
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->scal_host) (void)hipHostFree(h->scal_host);
+  for (hipEvent_t e : h->check_ev)
+    if (e) (void)hipEventDestroy(e);
   prof_flush(h);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
@@ -576,10 +578,15 @@ int stls_setup(int d, const int* nknots, const double* const* knots, const int* 
   alloc(&h->z, nb);
   alloc(&h->pvec, nb);
   alloc(&h->q, nb);
-  alloc(&h->partials, kPartialsCap * sizeof(double));
+  alloc(&h->partials, 2 * kPartialsCap * sizeof(double));  // two sets: dot products and r.r
   alloc(&h->dres, 8 * sizeof(double));
   if (!st && hipMalloc((void**)&h->scal, sizeof(PcgScalars)) != hipSuccess) { set_error("hipMalloc"); st = STLS_ENOMEM; }
-  if (!st && hipHostMalloc((void**)&h->scal_host, sizeof(PcgScalars), hipHostMallocDefault) != hipSuccess) {
+  for (int i = 0; i < 2 && !st; ++i)
+    if (hipEventCreateWithFlags(&h->check_ev[i], hipEventDisableTiming) != hipSuccess) {
+      set_error("hipEventCreate");
+      st = STLS_EHIP;
+    }
+  if (!st && hipHostMalloc((void**)&h->scal_host, 2 * sizeof(PcgScalars), hipHostMallocDefault) != hipSuccess) {
     set_error("hipHostMalloc");
     st = STLS_ENOMEM;
   }
@@ -654,7 +661,7 @@ int stls_pcg_history(stls_handle h, double* out, int max, int* count) {
 }
 
 static const char* kProfNames[PROF_COUNT] = {"fd_space", "fd_time", "mv_inner1", "mv_inner2", "mv_outer",
-                                             "vec", "reduce", "diff"};
+                                             "vec", "reduce", "diff", "fd_slab"};
 
 int stls_set_profiling(stls_handle h, int on) {
   if (!h) { set_error("NULL handle"); return STLS_EINVAL; }

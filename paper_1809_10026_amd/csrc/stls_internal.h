@@ -61,6 +61,8 @@ struct PcgScalars {
   double bnorm2;   // ||b||^2
   double relres;   // ||r||/||b||
   double rtol;
+  double rho_ring[2];  // r^T z by iteration parity (single-problem PCG: the update
+                       // kernels read one slot while another block writes the other)
   int done;        // set once relres <= rtol (later kernels become no-ops)
   int flag;        // 0 ok, 1 breakdown, 2 non-finite
   int iters;
@@ -76,6 +78,7 @@ enum ProfId {
   PROF_VEC,           // PCG vector kernels
   PROF_REDUCE,        // PCG scalar finalisation kernels
   PROF_DIFF,          // differentiation operators (load, transpose, mass, d/dkappa)
+  PROF_FD_SLAB,       // FD slab pass: modes 1 and 2 of every (i3, t) slab
   PROF_COUNT
 };
 
@@ -106,7 +109,10 @@ struct stls_ctx {
   int64_t nfull = 0;               // prod of full sizes m_k
   bool diff_ready = false;
   stls::PcgScalars* scal = nullptr;
-  stls::PcgScalars* scal_host = nullptr;  // pinned
+  stls::PcgScalars* scal_host = nullptr;  // pinned, 2 slots (convergence checks of alternate iterations)
+  hipEvent_t check_ev[2] = {nullptr, nullptr};
+  // set while a PCG solve runs: FD passes that see done or flag here return at once
+  const stls::PcgScalars* gate = nullptr;
   std::vector<double> history;
   int last_iters = 0;
   // profiling

@@ -96,7 +96,8 @@ template <typename TC, typename TI, typename TO, int NM, bool TRANS, bool WLDS, 
 __global__ __launch_bounds__(kThreads) void fd_mode_kernel(
     const TI* __restrict__ X, TO* __restrict__ Y, int L, int n, int ncols, const TC* __restrict__ Aop,
     const TC* __restrict__ Aop2, int w2lds, const double* __restrict__ lam_t, const double* __restrict__ lam_s,
-    const double* __restrict__ dotv, double* __restrict__ partials) {
+    const double* __restrict__ dotv, double* __restrict__ partials, const PcgScalars* __restrict__ gate) {
+  if (gate && (gate->done | gate->flag)) return;  // PCG already finished: nothing to do
   constexpr int NPAD = NM * 16;
   constexpr int PER = NPAD * kCols / kThreads;  // panel entries per thread
   constexpr bool PREF = NM <= 4;                // register prefetch of the next panel
@@ -274,7 +275,7 @@ __global__ __launch_bounds__(kThreads) void fd_mode_kernel(
 
 template <typename TC, typename TI, typename TO, bool TRANS, bool FUSED, bool DOT>
 using FdKernelPtr = void (*)(const TI*, TO*, int, int, int, const TC*, const TC*, int, const double*, const double*,
-                             const double*, double*);
+                             const double*, double*, const PcgScalars*);
 
 template <typename TC, typename TI, typename TO, bool TRANS, bool FUSED, bool DOT, int NM>
 static FdKernelPtr<TC, TI, TO, TRANS, FUSED, DOT> fd_pick(bool wlds) {
@@ -319,7 +320,7 @@ static int launch_fd_mode(stls_ctx* h, const TI* X, TO* Y, int L, int n, int nco
   }
   prof_begin(h);
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), shmem, h->stream, X, Y, L, n, ncols, A, A2, (int)w2lds, lam_t,
-                     h->lam_s, dotv, partials);
+                     h->lam_s, dotv, partials, h->gate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "fd_mode_kernel launch");
   prof_end(h, FUSED ? PROF_FD_TIME : PROF_FD_SPACE);
@@ -351,7 +352,8 @@ __global__ __launch_bounds__(kThreads) void fd_mode_bf16x3_kernel(
     const TI* __restrict__ X, TO* __restrict__ Y, int L, int n, int ncols, const unsigned short* __restrict__ Wh,
     const unsigned short* __restrict__ Wl, const unsigned short* __restrict__ W2h,
     const unsigned short* __restrict__ W2l, const double* __restrict__ lam_t, const double* __restrict__ lam_s,
-    const double* __restrict__ dotv, double* __restrict__ partials) {
+    const double* __restrict__ dotv, double* __restrict__ partials, const PcgScalars* __restrict__ gate) {
+  if (gate && (gate->done | gate->flag)) return;  // PCG already finished: nothing to do
   constexpr int NPAD = NM * 16;
   constexpr int NK = (NM + 1) / 2;  // 32-wide k steps
   constexpr int KPAD = NK * 32;
@@ -530,7 +532,8 @@ static int launch_fd_bf16(stls_ctx* h, const TI* X, TO* Y, int L, int n, int nco
   const unsigned short* W2h = FUSED ? h->dd[k2].Hbwd : nullptr;
   const unsigned short* W2l = FUSED ? h->dd[k2].Lbwd : nullptr;
   void (*kern)(const TI*, TO*, int, int, int, const unsigned short*, const unsigned short*, const unsigned short*,
-               const unsigned short*, const double*, const double*, const double*, double*) = nullptr;
+               const unsigned short*, const double*, const double*, const double*, double*,
+               const PcgScalars*) = nullptr;
 #define STLS_BF_PICK(NMV) \
   case NMV: kern = fd_mode_bf16x3_kernel<TI, TO, NMV, TRANS, FUSED, DOT>; break;
   switch (nm) {
@@ -546,7 +549,7 @@ static int launch_fd_bf16(stls_ctx* h, const TI* X, TO* Y, int L, int n, int nco
   }
   prof_begin(h);
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), shmem, h->stream, X, Y, L, n, ncols, Wh, Wl, W2h, W2l, lam_t,
-                     h->lam_s, dotv, partials);
+                     h->lam_s, dotv, partials, h->gate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "fd_mode_bf16x3_kernel launch");
   prof_end(h, FUSED ? PROF_FD_TIME : PROF_FD_SPACE);
@@ -1529,6 +1532,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(const double* __rest
       break;
     case FIN_RHO0:
       S->rho = s;
+      S->rho_ring[0] = s;
       if (!isfinite(s)) S->flag = 2;
       else if (!(s > 0.0)) S->flag = 1;
       break;
@@ -1554,37 +1558,114 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(const double* __rest
   }
 }
 
-// x += alpha p; r -= alpha q; partial sums of r.r
+// Sum of nparts partial sums in a fixed order (identical in every block).
+__device__ inline double sum_partials(const double* __restrict__ partials, int nparts, double* red) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += partials[i];
+  v = block_sum(v, red);
+  __syncthreads();
+  if (threadIdx.x == 0) red[0] = v;
+  __syncthreads();
+  return red[0];
+}
+
+// Iteration k (parity par = k & 1): alpha = rho_{k-1} / (p.q) from the
+// matvec's partial sums (every block forms the same sum; block 0 records
+// alpha and any breakdown), then x += alpha p; r -= alpha q; partial sums of
+// r.r into rr_parts.
 __global__ __launch_bounds__(kThreads) void update_xr_kernel(double* __restrict__ x, double* __restrict__ r,
                                                              const double* __restrict__ p,
                                                              const double* __restrict__ q, int n,
-                                                             const PcgScalars* __restrict__ S,
-                                                             double* __restrict__ partials) {
+                                                             PcgScalars* __restrict__ S,
+                                                             const double* __restrict__ pq_parts, int npq, int par,
+                                                             double* __restrict__ rr_parts) {
   __shared__ double red[4];
-  if (S->done || S->flag) return;
-  const double alpha = S->alpha;
+  // block 0 of this kernel may set S->flag while other blocks start: decide
+  // once per block (thread 0) so that every wave of a block takes the same path
+  __shared__ int skip;
+  if (threadIdx.x == 0) skip = S->done | S->flag;
+  __syncthreads();
+  if (skip) return;
+  const double pq = sum_partials(pq_parts, npq, red);
+  const bool bad = !isfinite(pq) || !(pq > 0.0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (!isfinite(pq)) S->flag = 2;
+    else if (!(pq > 0.0)) S->flag = 1;
+    else S->alpha = S->rho_ring[par ^ 1] / pq;
+  }
+  if (bad) return;
+  const double alpha = S->rho_ring[par ^ 1] / pq;
   double s = 0.0;
-  for (int e = blockIdx.x * kThreads + threadIdx.x; e < n; e += gridDim.x * kThreads) {
-    x[e] += alpha * p[e];
-    const double rn = r[e] - alpha * q[e];
-    r[e] = rn;
+  // 16-byte accesses (pairs; the internal vectors are 256-byte aligned).  x is
+  // the caller's buffer: pairs when it is 16-byte aligned, else two scalars;
+  // the r.r summation order is the same either way.
+  const int n2 = n >> 1;
+  const bool xal = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+  double2* r2 = reinterpret_cast<double2*>(r);
+  const double2* p2 = reinterpret_cast<const double2*>(p);
+  const double2* q2 = reinterpret_cast<const double2*>(q);
+  for (int e = blockIdx.x * kThreads + threadIdx.x; e < n2; e += gridDim.x * kThreads) {
+    const double2 pv = p2[e], rv = r2[e], qv = q2[e];
+    if (xal) {
+      double2* x2 = reinterpret_cast<double2*>(x);
+      const double2 xv = x2[e];
+      x2[e] = make_double2(xv.x + alpha * pv.x, xv.y + alpha * pv.y);
+    } else {
+      x[2 * e] += alpha * pv.x;
+      x[2 * e + 1] += alpha * pv.y;
+    }
+    const double2 rn = make_double2(rv.x - alpha * qv.x, rv.y - alpha * qv.y);
+    r2[e] = rn;
+    s += rn.x * rn.x + rn.y * rn.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {  // odd tail
+    x[n - 1] += alpha * p[n - 1];
+    const double rn = r[n - 1] - alpha * q[n - 1];
+    r[n - 1] = rn;
     s += rn * rn;
   }
   s = block_sum(s, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) rr_parts[blockIdx.x] = s;
 }
 
-// p = z + beta p
+// Iteration k (parity par): rho_k = r.z from the FD's partial sums, beta =
+// rho_k / rho_{k-1}; block 0 stores rho_k in the ring slot par (the other
+// blocks read slot par ^ 1 only); p = z + beta p.
 __global__ __launch_bounds__(kThreads) void update_p_kernel(double* __restrict__ p, const double* __restrict__ z,
-                                                            int n, const PcgScalars* __restrict__ S) {
-  if (S->done || S->flag) return;
-  const double beta = S->beta;
-  for (int e = blockIdx.x * kThreads + threadIdx.x; e < n; e += gridDim.x * kThreads) p[e] = z[e] + beta * p[e];
+                                                            int n, PcgScalars* __restrict__ S,
+                                                            const double* __restrict__ rz_parts, int nrz, int par) {
+  __shared__ double red[4];
+  __shared__ int skip;  // block-uniform decision (see update_xr_kernel)
+  if (threadIdx.x == 0) skip = S->done | S->flag;
+  __syncthreads();
+  if (skip) return;
+  const double rz = sum_partials(rz_parts, nrz, red);
+  const bool bad = !isfinite(rz) || !(rz > 0.0);
+  const double beta = rz / S->rho_ring[par ^ 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (!isfinite(rz)) S->flag = 2;
+    else if (!(rz > 0.0)) S->flag = 1;
+    else {
+      S->beta = beta;
+      S->rho = rz;
+      S->rho_ring[par] = rz;
+    }
+  }
+  if (bad) return;
+  const int n2 = n >> 1;
+  double2* p2 = reinterpret_cast<double2*>(p);
+  const double2* z2 = reinterpret_cast<const double2*>(z);
+  for (int e = blockIdx.x * kThreads + threadIdx.x; e < n2; e += gridDim.x * kThreads) {
+    const double2 pv = p2[e], zv = z2[e];
+    p2[e] = make_double2(zv.x + beta * pv.x, zv.y + beta * pv.y);
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) p[n - 1] = z[n - 1] + beta * p[n - 1];  // odd tail
 }
 
 __global__ void init_scalars_kernel(PcgScalars* S, double rtol) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     S->rho = S->alpha = S->beta = S->bnorm2 = 0.0;
+    S->rho_ring[0] = S->rho_ring[1] = 0.0;
     S->relres = 1.0;
     S->rtol = rtol;
     S->done = S->flag = S->iters = S->pad = 0;
@@ -1592,6 +1673,9 @@ __global__ void init_scalars_kernel(PcgScalars* S, double rtol) {
 }
 
 static int ew_blocks(int n) { return std::max(1, std::min((n + kThreads - 1) / kThreads, kMaxBlocksEW)); }
+// grid of the PCG vector kernels: few enough partial sums for a quick
+// single-workgroup finalisation, enough workgroups to stream at full rate
+static int vec_blocks(int n) { return std::max(1, std::min((n + kThreads - 1) / kThreads, 2048)); }
 
 static int fin(stls_ctx* h, int nparts, int kind, double* hist, int it) {
   prof_begin(h);
@@ -1613,7 +1697,7 @@ static int read_scalars(stls_ctx* h) {
 
 int pcg_run(stls_ctx* h, const double* b, double* x, double rtol, int maxit, int* iters, double* relres) {
   const int N = (int)h->ndof;
-  const int nb = ew_blocks(N);
+  const int nb = vec_blocks(N);
   int st, np = 0;
   hipError_t e;
   h->history.clear();
@@ -1641,28 +1725,50 @@ int pcg_run(stls_ctx* h, const double* b, double* x, double rtol, int maxit, int
   if ((st = fin(h, np, FIN_RHO0, nullptr, 0))) return st;
   e = hipMemcpyAsync(h->pvec, h->z, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  // Iteration k enqueues its convergence check (scalars copied to a pinned
+  // slot, event) and then, before waiting on it, the preconditioner and the
+  // direction update of the same iteration: while the host waits and then
+  // enqueues iteration k + 1, the GPU runs the FD chain.  Once the check
+  // reports convergence those already-enqueued kernels return at once (they
+  // read done through the gate / the scalars).
+  double* rr_parts = h->partials + kPartialsCap;
   int k = 0;
   int status = STLS_ENOCONV;
+  h->gate = h->scal;
   for (k = 1; k <= maxit; ++k) {
-    if ((st = launch_matvec(h, h->pvec, h->q, h->pvec, h->partials, &np))) return st;
-    if ((st = fin(h, np, FIN_ALPHA, nullptr, k))) return st;
+    const int par = k & 1;
+    if ((st = launch_matvec(h, h->pvec, h->q, h->pvec, h->partials, &np))) break;
     prof_begin(h);
     hipLaunchKernelGGL(update_xr_kernel, dim3(nb), dim3(kThreads), 0, h->stream, x, h->r, h->pvec, h->q, N, h->scal,
-                       h->partials);
+                       h->partials, np, par, rr_parts);
     prof_end(h, PROF_VEC);
-    if ((st = fin(h, nb, FIN_RR, nullptr, k))) return st;
-    if ((st = read_scalars(h))) return st;
-    if (S->flag == 2) { set_error("non-finite value in PCG"); status = STLS_ENAN; break; }
-    if (S->flag == 1) { set_error("PCG breakdown (non-positive curvature)"); status = STLS_EBREAKDOWN; break; }
-    h->history.push_back(S->relres);
-    if (S->done) { status = STLS_OK; break; }
-    if (k == maxit) break;
-    if ((st = launch_prec_apply(h, h->r, h->z, h->r, h->partials, &np))) return st;
-    if ((st = fin(h, np, FIN_BETA, nullptr, k))) return st;
+    if ((e = hipGetLastError()) != hipSuccess) { st = hip_fail(e, "update_xr_kernel launch"); break; }
     prof_begin(h);
-    hipLaunchKernelGGL(update_p_kernel, dim3(nb), dim3(kThreads), 0, h->stream, h->pvec, h->z, N, h->scal);
-    prof_end(h, PROF_VEC);
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kThreads), 0, h->stream, rr_parts, nb, h->scal, (int)FIN_RR,
+                       nullptr, k);
+    prof_end(h, PROF_REDUCE);
+    if ((e = hipGetLastError()) != hipSuccess) { st = hip_fail(e, "finalize_kernel launch"); break; }
+    e = hipMemcpyAsync(h->scal_host + par, h->scal, sizeof(PcgScalars), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(h->check_ev[par], h->stream);
+    if (e != hipSuccess) { st = hip_fail(e, "scalar read-back"); break; }
+    if (k < maxit) {
+      if ((st = launch_prec_apply(h, h->r, h->z, h->r, h->partials, &np))) break;
+      prof_begin(h);
+      hipLaunchKernelGGL(update_p_kernel, dim3(nb), dim3(kThreads), 0, h->stream, h->pvec, h->z, N, h->scal,
+                         h->partials, np, par);
+      prof_end(h, PROF_VEC);
+      if ((e = hipGetLastError()) != hipSuccess) { st = hip_fail(e, "update_p_kernel launch"); break; }
+    }
+    if ((e = hipEventSynchronize(h->check_ev[par])) != hipSuccess) { st = hip_fail(e, "hipEventSynchronize"); break; }
+    const PcgScalars* Sk = h->scal_host + par;
+    if (Sk->flag == 2) { set_error("non-finite value in PCG"); status = STLS_ENAN; break; }
+    if (Sk->flag == 1) { set_error("PCG breakdown (non-positive curvature)"); status = STLS_EBREAKDOWN; break; }
+    h->history.push_back(Sk->relres);
+    if (Sk->done) { status = STLS_OK; break; }
   }
+  h->gate = nullptr;
+  if (st) return st;
+  if ((st = read_scalars(h))) return st;  // drains the stream; final scalars
   const int done_iters = (int)h->history.size() - 1;
   if (iters) *iters = done_iters;
   if (relres) *relres = S->relres;

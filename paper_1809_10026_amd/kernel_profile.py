@@ -1,0 +1,55 @@
+"""Kernel workload for rocprofv3: one calibration copy and a few PCG solves.
+
+    rocprofv3 --kernel-trace --stats -d OUT -o run -- python3 -m paper_1809_10026_amd.kernel_profile
+    rocprofv3 --pmc FETCH_SIZE -d OUT -o run -- python3 -m paper_1809_10026_amd.kernel_profile
+    rocprofv3 --pmc WRITE_SIZE -d OUT -o run -- python3 -m paper_1809_10026_amd.kernel_profile
+
+The calibration kernel is an elementwise multiply that reads one 256 MiB
+FP64 buffer and writes another (a plain copy of known size, launched as a
+kernel rather than a DMA-engine copy); its FETCH_SIZE and WRITE_SIZE readings
+give the factors that turn the counters into HBM bytes.  Then the d = 3,
+p = 4, 48-element workload (ndof 6,375,000) is solved with the BF16x3 FD
+preconditioner (the benchmark's headline mode) ``--solves`` times.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+CALIB_BYTES = 256 * 1024 * 1024
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--solves", type=int, default=2)
+    ap.add_argument("--mode", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
+    args = ap.parse_args()
+    import torch
+
+    import paper_1809_10026_amd as stls
+    from stls_inputs import CONFIGS, problem_knots, uniform_pm1
+
+    src = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(f"[kernel_profile] calibration copy: {CALIB_BYTES} bytes read and written per launch", flush=True)
+    del src, dst
+
+    cfg = CONFIGS["d3_p4_nel48"]
+    S = stls.Solver(*problem_knots(cfg["d"], cfg["n_el"], cfg["p"]))
+    S.set_fd_precision({"fp64": stls.STLS_FD_FP64, "fp32": stls.STLS_FD_FP32, "bf16x3": stls.STLS_FD_BF16X3}[args.mode])
+    b = torch.as_tensor(uniform_pm1(S.ndof, cfg["seed"])).cuda()
+    x = torch.empty_like(b)
+    for i in range(args.solves):
+        _, it, rel = S.solve(b, cfg["rtol"], 200, out=x)
+        torch.cuda.synchronize()
+        print(f"[kernel_profile] solve {i}: {it} iterations, relres {rel:.2e}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -223,3 +223,24 @@ def test_pcg_zero_rhs_and_noconv():
     with pytest.raises(stls.StlsError) as ei:
         S.solve(b)
     assert ei.value.status == stls.STLS_ENAN
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_pcg_output_alignment_and_history(mode):
+    """The solution vector may be any 8-byte-aligned device buffer (here a view
+    one element into a larger tensor, so not 16-byte aligned): same iterate as
+    an aligned output; the residual history starts at 1, has one entry per
+    iteration and ends at the returned relative residual."""
+    import torch
+    knots, degs = problem_knots(3, 8, 4)
+    S = _lib().Solver(knots, degs)
+    S.set_fd_precision(mode)
+    b = to_dev(uniform_pm1(S.ndof, 31))
+    x_al, it_al, rel_al = S.solve(b, rtol=1e-9)
+    buf = torch.zeros(S.ndof + 1, dtype=torch.float64, device="cuda")
+    x_un = buf[1:]
+    _, it_un, rel_un = S.solve(b, rtol=1e-9, out=x_un)
+    assert it_un == it_al and rel_un == rel_al
+    assert float((x_un - x_al).abs().max()) == 0.0
+    hist = S.history()
+    assert len(hist) == it_al + 1 and hist[0] == 1.0 and hist[-1] == rel_un <= 1e-9
