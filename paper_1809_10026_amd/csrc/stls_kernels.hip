@@ -1121,13 +1121,18 @@ __global__ __launch_bounds__(kSlabWaves * 64) void mv_inner_slab_kernel(
         const double* cm = M2 + rr * BW;
         const double* cj = J2 + rr * BW;
         const double* ck = K2 + rr * BW;
-        double a = 0.0, b = 0.0, c = 0.0;
+        // independent partial sums (short dependent FMA chains)
+        double a = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0, c1 = 0.0, c2 = 0.0;
 #pragma unroll
         for (int o = 0; o < BW; ++o) {
           a += cm[o] * m[r + o];
-          b += cj[o] * m[r + o] + cm[o] * jv[r + o] + 2.0 * ck[o] * kv[r + o];
-          c += ck[o] * m[r + o] + cm[o] * kv[r + o];
+          b1 += cj[o] * m[r + o];
+          b2 += cm[o] * jv[r + o];
+          b3 += ck[o] * kv[r + o];
+          c1 += ck[o] * m[r + o];
+          c2 += cm[o] * kv[r + o];
         }
+        const double b = (b1 + b2) + 2.0 * b3, c = c1 + c2;
         if (lane < n1 && r0 + r < n2) {
           const size_t g = base + (size_t)(r0 + r) * n1 + lane;
           A[g] = a;
@@ -1167,7 +1172,7 @@ __device__ inline void wait_vmcnt() {
 }
 
 template <int PT, int P, int K, bool DOT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void mv_outer_dma_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void mv_outer_dma_kernel(
     const double* __restrict__ A, const double* __restrict__ B, const double* __restrict__ C, double* __restrict__ y,
     int L, int nd, int nt, int Td, int nlb, int ntd, int nchunk, int Tc, const double* __restrict__ Md,
     const double* __restrict__ Jd, const double* __restrict__ Kd, const double* __restrict__ Kt,
@@ -1255,7 +1260,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     issue(t + D - 1, (t + D - 1) % D);  // always K copies (clamped slices past the end)
     const double* buf = sm + (t % D) * slot;
     if (t <= tl) {  // uniform
-      double x1 = 0.0, x2 = 0.0, x3 = 0.0;
+      // four independent partial sums: no long dependent FMA chain per step
+      double x1 = 0.0, xa = 0.0, xb = 0.0, xc = 0.0;
 #pragma unroll
       for (int o = 0; o < BW; ++o) {
         const int rr = drc + o;
@@ -1263,11 +1269,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const double b = buf[arr + rr * LB + li];
         const double c = buf[2 * arr + rr * LB + li];
         x1 += cm[o] * a;
-        x2 += cj[o] * a + cm[o] * b + 2.0 * ck[o] * c;
-        x3 += ck[o] * a + cm[o] * c;
+        xa += cj[o] * a;
+        xb += cm[o] * b;
+        xc += ck[o] * c;
       }
-      const double s1 = x1, s2 = k2 * x2;
-      if (t == nt - 1) s3 = kw * x3;
+      const double s1 = x1, s2 = k2 * ((xa + xb) + 2.0 * xc);
+      if (t == nt - 1) {  // final-time term, last slice only (uniform)
+        double x3 = 0.0;
+#pragma unroll
+        for (int o = 0; o < BW; ++o) x3 += ck[o] * buf[(drc + o) * LB + li] + cm[o] * buf[2 * arr + (drc + o) * LB + li];
+        s3 = kw * x3;
+      }
       const double* kt = Kt + t * W;
       const double* mt = Mt + t * W;
 #pragma unroll
@@ -1320,7 +1332,10 @@ static int launch_inner_slab(stls_ctx* h, const double* x, hipError_t* err) {
   const int nslab = (int)(h->ndof / ((int64_t)n1 * n2));
   double** w = h->work;
   prof_begin(h);
-  hipLaunchKernelGGL(kern, dim3(nslab), dim3(kSlabWaves * 64), shmem, h->stream, x, w[0], w[1], w[2], n1, n2, nslab,
+  // persistent grid (two workgroups per CU by LDS): each workgroup prefetches
+  // its next slab into registers while it processes the current one
+  const int blocks = std::min(nslab, 2 * 256);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(kSlabWaves * 64), shmem, h->stream, x, w[0], w[1], w[2], n1, n2, nslab,
                      ld, D1.M, D1.J, D1.K, D2.M, D2.J, D2.K);
   *err = hipGetLastError();
   prof_end(h, PROF_MV_INNER2);
