@@ -36,6 +36,29 @@ __device__ inline void split8(const float* v, bf8_t& h, bf8_t& l) {
   }
 }
 __device__ inline bf8_t ld8(const void* p) { return *reinterpret_cast<const bf8_t*>(p); }
+
+// Range-checked buffer access: a lane whose byte offset lies past the
+// buffer's size is dropped by the hardware (store) or reads 0 (load), with no
+// memory access.  Every lane issues the instruction, so a wave issues a fixed
+// number of memory operations per work item whatever the padding, and the
+// compiler can wait for exactly the prefetched loads (on gfx9 one counter
+// covers loads and stores).  Word 3 of the resource: 32-bit data format,
+// no swizzle.
+constexpr int kBufWord3 = 0x00020000;
+constexpr int kOutOfRange = 0x7fffffff;  // beyond every buffer used here (all < 2 GiB)
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufWord3);
+}
+__device__ inline void buf_store(float v, __amdgpu_buffer_rsrc_t r, int off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+}
+__device__ inline void buf_store(double v, __amdgpu_buffer_rsrc_t r, int off) {
+  typedef unsigned int u2_t __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, v), r, off, 0, 0);
+}
+__device__ inline float buf_load_f32(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
 __device__ inline f4v mfma3(bf8_t ah, bf8_t al, bf8_t bh, bf8_t bl, f4v c) {
   c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
   c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
@@ -94,16 +117,17 @@ __global__ __launch_bounds__(256) void fd_slab_bf16_kernel(const TI* __restrict_
     for (int kb = 0; kb < NK; ++kb)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
+        // raw loads (columns past n1 read the row start and are zeroed at use):
+        // no select right after the load, which would force an early wait
         const int c0 = 32 * kb + 8 * g + 2 * q;  // n1 even: pairs never straddle a row
-        const bool ok = c0 < n1;
         if constexpr (sizeof(TI) == 8) {
-          const double2 w = *reinterpret_cast<const double2*>(row + (ok ? c0 : 0));
-          px[kb][2 * q] = ok ? w.x : 0.0;
-          px[kb][2 * q + 1] = ok ? w.y : 0.0;
+          const double2 w = *reinterpret_cast<const double2*>(row + (c0 < n1 ? c0 : 0));
+          px[kb][2 * q] = w.x;
+          px[kb][2 * q + 1] = w.y;
         } else {
-          const float2 w = *reinterpret_cast<const float2*>(row + (ok ? c0 : 0));
-          px[kb][2 * q] = ok ? w.x : 0.f;
-          px[kb][2 * q + 1] = ok ? w.y : 0.f;
+          const float2 w = *reinterpret_cast<const float2*>(row + (c0 < n1 ? c0 : 0));
+          px[kb][2 * q] = w.x;
+          px[kb][2 * q + 1] = w.y;
         }
       }
   };
@@ -127,7 +151,7 @@ __global__ __launch_bounds__(256) void fd_slab_bf16_kernel(const TI* __restrict_
     for (int kb = 0; kb < NK; ++kb) {
       float v[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (float)px[kb][e];
+      for (int e = 0; e < 8; ++e) v[e] = 32 * kb + 8 * g + e < n1 ? (float)px[kb][e] : 0.f;
       split8(v, xh[kb], xl[kb]);
     }
     fetch(min(sl + (int)gridDim.x, nslab - 1));  // always issued: uniform load order
@@ -152,6 +176,7 @@ __global__ __launch_bounds__(256) void fd_slab_bf16_kernel(const TI* __restrict_
       *reinterpret_cast<bf4_t*>(yl + o) = ll;
     }
     __syncthreads();
+    const __amdgpu_buffer_rsrc_t zr = buf_rsrc(Z + base, (size_t)ns * sizeof(TO));  // this slab of Z
 #pragma unroll
     for (int nt = 0; nt < NM; ++nt) {
       f4v acc = f4v{0.f, 0.f, 0.f, 0.f};
@@ -161,15 +186,12 @@ __global__ __launch_bounds__(256) void fd_slab_bf16_kernel(const TI* __restrict_
         acc = mfma3(a2h[kb], a2l[kb], ld8(yh + o), ld8(yl + o), acc);
       }
       const int j1 = 16 * nt + cl;
-      if (j1 < n1) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (j2o + r < n2) {
-            const TO zv = (TO)acc[r];
-            if constexpr (DOT) dsum += (double)zv * dv[nt * 4 + r];
-            Z[base + (size_t)(j2o + r) * n1 + j1] = zv;
-          }
-        }
+      for (int r = 0; r < 4; ++r) {
+        const bool ok = j1 < n1 && j2o + r < n2;
+        const TO zv = (TO)acc[r];
+        if constexpr (DOT) dsum += ok ? (double)zv * dv[nt * 4 + r] : 0.0;
+        buf_store(zv, zr, ok ? (int)(((j2o + r) * n1 + j1) * sizeof(TO)) : kOutOfRange);
       }
     }
     buf ^= 1;
@@ -207,9 +229,29 @@ __global__ __launch_bounds__(kStridedWaves * 64) void fd_strided_bf16_kernel(
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, cl = lane & 15;
-  float* myscr = reinterpret_cast<float*>(smem_raw) + wave * 16 * LDS_S;
+  // fused kernel LDS: lambda_t (16 NM doubles, clamped), the backward
+  // operator's bf16 halves [16 NM][KPAD + 8] (registers hold the forward one),
+  // then the per-wave scratch tiles
+  constexpr int LDV = KPAD + 8;
+  double* lt_lds = reinterpret_cast<double*>(smem_raw);
+  __bf16* v2h = reinterpret_cast<__bf16*>(smem_raw + 16 * NM * sizeof(double));
+  __bf16* v2l = v2h + 16 * NM * LDV;
+  float* myscr = reinterpret_cast<float*>(smem_raw + (FUSED ? 16 * NM * sizeof(double) + 2 * 16 * NM * LDV * 2 : 0)) +
+                 wave * 16 * LDS_S;
+  if constexpr (FUSED) {
+    for (int i = threadIdx.x; i < 16 * NM; i += blockDim.x) lt_lds[i] = lam_t[min(i, n - 1)];
+    for (int e = threadIdx.x; e < 16 * NM * KPAD; e += blockDim.x) {
+      const int i = e / KPAD, k = e - i * KPAD;
+      v2h[i * LDV + k] = W2h[e];
+      v2l[i * LDV + k] = W2l[e];
+    }
+    __syncthreads();
+  }
+  const int nunits = (ncols + 15) / 16;
+  const int stride = gridDim.x * kStridedWaves;
+  const int u0 = blockIdx.x * kStridedWaves + wave;
+  if (u0 >= nunits) return;
   bf8_t wh[NM][NK], wl[NM][NK];
-  bf8_t vh[FUSED ? NM : 1][NK], vl[FUSED ? NM : 1][NK];
 #pragma unroll
   for (int t = 0; t < NM; ++t)
 #pragma unroll
@@ -217,31 +259,36 @@ __global__ __launch_bounds__(kStridedWaves * 64) void fd_strided_bf16_kernel(
       const int off = (16 * t + cl) * KPAD + 32 * kb + 8 * g;
       wh[t][kb] = ld8(Wh + off);
       wl[t][kb] = ld8(Wl + off);
-      if constexpr (FUSED) {
-        vh[t][kb] = ld8(W2h + off);
-        vl[t][kb] = ld8(W2l + off);
-      }
     }
-  const int nunits = (ncols + 15) / 16;
+  // the operator fragments arrive before the column prefetch is issued:
+  // were they queued behind it, the loop's waits (taken over the entry path
+  // as well) would drain the whole prefetch on every unit
+  __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8));  // vmcnt(0)
+  __builtin_amdgcn_sched_barrier(0);
   const int Ln = L * n;
   auto base_of = [&](int c) -> int { return (c % L) + (c / L) * Ln; };
+  const __amdgpu_buffer_rsrc_t xr = buf_rsrc(X, (size_t)ncols * n * sizeof(float));
+  const __amdgpu_buffer_rsrc_t yr = buf_rsrc(Y, (size_t)ncols * n * sizeof(float));
   float pv[DEPTH][NK][8];
-  auto fetch = [&](int u, float (&v)[NK][8]) {
+  // fused: lambda_s of the prefetched column, loaded after the unit's last
+  // use of the slot (so the slot needs no second register and no copy)
+  double pls[DEPTH];
+  auto fetch = [&](int u, float (&v)[NK][8]) {  // rows k >= n read as 0 (out of range)
     const int b = base_of(min(u * 16 + cl, ncols - 1));
 #pragma unroll
     for (int kb = 0; kb < NK; ++kb)
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int k = 32 * kb + 8 * g + e;
-        const float x = X[b + min(k, n - 1) * L];
-        v[kb][e] = k < n ? x : 0.f;
+        v[kb][e] = buf_load_f32(xr, k < n ? (b + k * L) * (int)sizeof(float) : kOutOfRange);
       }
   };
-  const int stride = gridDim.x * kStridedWaves;
-  const int u0 = blockIdx.x * kStridedWaves + wave;
-  if (u0 >= nunits) return;
 #pragma unroll
-  for (int d = 0; d < DEPTH; ++d) fetch(min(u0 + d * stride, nunits - 1), pv[d]);
+  for (int d = 0; d < DEPTH; ++d) {
+    fetch(min(u0 + d * stride, nunits - 1), pv[d]);
+    if constexpr (FUSED) pls[d] = lam_s[min(min(u0 + d * stride, nunits - 1) * 16 + cl, ncols - 1)];
+    __builtin_amdgcn_sched_barrier(0);  // issue order as in the loop: unit by unit
+  }
   for (int ub = u0; ub < nunits; ub += DEPTH * stride) {
 #pragma unroll
     for (int d = 0; d < DEPTH; ++d) {
@@ -250,7 +297,9 @@ __global__ __launch_bounds__(kStridedWaves * 64) void fd_strided_bf16_kernel(
       bf8_t xh[NK], xl[NK];
 #pragma unroll
       for (int kb = 0; kb < NK; ++kb) split8(pv[d][kb], xh[kb], xl[kb]);
+      __builtin_amdgcn_sched_barrier(0);
       fetch(min(u + DEPTH * stride, nunits - 1), pv[d]);  // always issued: uniform load order
+      __builtin_amdgcn_sched_barrier(0);
       f4v acc[NM];
 #pragma unroll
       for (int t = 0; t < NM; ++t) {
@@ -259,7 +308,6 @@ __global__ __launch_bounds__(kStridedWaves * 64) void fd_strided_bf16_kernel(
         for (int kb = 0; kb < NK; ++kb) acc[t] = mfma3(wh[t][kb], wl[t][kb], xh[kb], xl[kb], acc[t]);
       }
       if constexpr (FUSED) {
-        const double ls = lam_s[min(c, ncols - 1)];
 #pragma unroll
         for (int t = 0; t < NM; ++t) {
           f4v q;
@@ -268,8 +316,8 @@ __global__ __launch_bounds__(kStridedWaves * 64) void fd_strided_bf16_kernel(
             // the quotient is rounded to FP32 at once: an FP32 reciprocal of
             // the FP64 eigenvalue sum loses nothing the bf16x3 products keep
             const int i = 16 * t + 4 * g + r;
-            const float den = (float)(lam_t[min(i, n - 1)] + ls);
-            q[r] = i < n ? acc[t][r] * __builtin_amdgcn_rcpf(den) : 0.f;
+            const float qv = acc[t][r] * __builtin_amdgcn_rcpf((float)(lt_lds[i] + pls[d]));
+            q[r] = i < n ? qv : 0.f;
           }
           *reinterpret_cast<f4v*>(myscr + cl * LDS_S + 16 * t + 4 * g) = q;
         }
@@ -292,19 +340,24 @@ __global__ __launch_bounds__(kStridedWaves * 64) void fd_strided_bf16_kernel(
         for (int t = 0; t < NM; ++t) {
           acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-          for (int kb = 0; kb < NK; ++kb) acc[t] = mfma3(vh[t][kb], vl[t][kb], xh[kb], xl[kb], acc[t]);
+          for (int kb = 0; kb < NK; ++kb) {
+            const int o = (16 * t + cl) * LDV + 32 * kb + 8 * g;
+            acc[t] = mfma3(ld8(v2h + o), ld8(v2l + o), xh[kb], xl[kb], acc[t]);
+          }
         }
       }
-      if (u < nunits && c < ncols) {
-        const int b = base_of(c);
+      {
+        const bool colok = u < nunits && c < ncols;
+        const int b = base_of(min(c, ncols - 1));
 #pragma unroll
         for (int t = 0; t < NM; ++t)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int i = 16 * t + 4 * g + r;
-            if (i < n) Y[b + i * L] = acc[t][r];
+            buf_store(acc[t][r], yr, colok && i < n ? (b + i * L) * (int)sizeof(float) : kOutOfRange);
           }
       }
+      if constexpr (FUSED) pls[d] = lam_s[min(min(u + DEPTH * stride, nunits - 1) * 16 + cl, ncols - 1)];
     }
   }
 }
@@ -339,7 +392,9 @@ int launch_strided(stls_ctx* h, const float* X, float* Y, int L, int k, bool fwd
   const int nunits = (ncols + 15) / 16;
   const int blocks = std::max(1, std::min((nunits + kStridedWaves - 1) / kStridedWaves, 256));
   constexpr int NK = (NM + 1) / 2;
-  const size_t shmem = FUSED ? sizeof(float) * kStridedWaves * 16 * (NK * 32 + 4) : 0;
+  const size_t shmem = FUSED ? sizeof(double) * 16 * NM + sizeof(__bf16) * 2 * 16 * NM * (NK * 32 + 8) +
+                                  sizeof(float) * kStridedWaves * 16 * (NK * 32 + 4)
+                             : 0;
   const __bf16* Wh = (const __bf16*)(fwd ? D.Hfwd : D.Hbwd);
   const __bf16* Wl = (const __bf16*)(fwd ? D.Lfwd : D.Lbwd);
   const __bf16* W2h = FUSED ? (const __bf16*)D.Hbwd : nullptr;
@@ -378,13 +433,14 @@ int slab_nm(stls_ctx* h, const TI* X, TO* Z, bool fwd, const double* dotv, doubl
 }  // namespace
 
 // Shapes covered: d = 3, every restricted size <= 64, n1 even, directions 1
-// and 2 padded alike, L = n1 n2 n3 and n1 n2 products fitting 32-bit offsets.
+// and 2 padded alike, and the FP32 work vectors addressable by one buffer
+// resource (byte offsets below 2^31; out-of-range lanes use 0x7fffffff).
 bool fd_bf16_five_pass_covers(const stls_ctx* h) {
   if (h->d != 3) return false;
   for (int k = 0; k <= 3; ++k)
     if (h->dir[k].n > 64) return false;
   if (h->dir[0].n % 2 != 0 || h->dd[0].npad != h->dd[1].npad) return false;
-  return h->ndof < ((int64_t)1 << 31);
+  return h->ndof * (int64_t)sizeof(float) < ((int64_t)1 << 31) - 1;
 }
 
 int prec_apply_bf16x3_five_pass(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
