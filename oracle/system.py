@@ -103,6 +103,22 @@ class Problem:
             terms.append((kap * kap, fac + [Tm["Mhat"]]))
         return terms
 
+    def kron_diagonal(self, terms):
+        """Diagonal of sum_c c (W_{d+1} x ... x W_1) as a tensor of self.shape.
+
+        The diagonal of a Kronecker product is the Kronecker product of the
+        factors' diagonals, so each term contributes c times the outer product
+        of diag(W_m) over the modes m."""
+        D = np.zeros(self.shape)
+        for c, facs in terms:
+            t = np.ones(self.shape)
+            for m, W in enumerate(facs):
+                sh = [1] * (self.d + 1)
+                sh[m] = W.shape[0]
+                t = t * np.diag(W).reshape(sh)
+            D = D + c * t
+        return D
+
     # --- operators ------------------------------------------------------
     def matvec(self, X):
         """A_kappa vec(X) as a sum of mode-product chains (tensor in, tensor out)."""
