@@ -161,6 +161,16 @@ def main():
     mv_s = (time.perf_counter() - t) / 20
     err_vs_fp64 = {m: float(torch.linalg.norm(sol[m] - sol["fp64"]) / torch.linalg.norm(sol["fp64"]))
                    for m in ("fp32", "bf16x3")}
+    # the diagonally scaled preconditioner D^-1/2 P^-1 D^-1/2 (§4.4), same solves
+    scaled = {}
+    S.set_fd_scaling(True)
+    for name in ("fp64", "bf16x3"):
+        dt, it, rel, _ = timed_solves(modes[name], args.steps, args.warmup, profile=False)
+        scaled[name] = dict(time_to_tol_s=dt, iters=it, relres=rel, true_relres=true_relres(x),
+                            err_vs_fp64_solution=float(torch.linalg.norm(x - sol["fp64"]) / torch.linalg.norm(sol["fp64"])),
+                            fd_prec_dof_per_s=N / fd_rate(modes[name]))
+        log(f"{name} scaled: solve {dt*1e3:.3f} ms, {it} its, true {scaled[name]['true_relres']:.2e}")
+    S.set_fd_scaling(False)
 
     # roofline of the dominant kernel class of the headline (timed) solves
     prof = res[mixed]["prof"]
@@ -215,6 +225,7 @@ def main():
         "err_vs_fp64_solution": err_vs_fp64,
         "fd_prec_dof_per_s": {k: N / v["fd_apply_s"] for k, v in res.items()},
         "matvec_dof_per_s": N / mv_s,
+        "diag_scaled_prec": scaled,
         "setup_s": setup_s,
         "roofline": roofline,
         "roofline_note": "kernel durations from HIP events recorded around every launch on the solver's "

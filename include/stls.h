@@ -106,6 +106,17 @@ int stls_set_kappa(stls_handle h, double kappa);
 int stls_set_fd_precision(stls_handle h, int mode);
 
 /*
+ * Diagonal scaling of the preconditioner (§4.4, closing definition):
+ * P^G = D^{1/2} P D^{1/2} with D_ii = A_ii / P_ii.  On the unit box the
+ * geometry-approximated factor of §4.4 is P itself, so with on != 0
+ * stls_prec_apply and stls_pcg_solve use s = D^{-1/2} P^{-1} D^{-1/2} r.
+ * D is formed on the fly from the univariate diagonals and follows
+ * stls_set_kappa; on = 0 (the default) restores s = P^{-1} r.  Batched
+ * solves (stls_batch_*) always use the unscaled P.
+ */
+int stls_set_fd_scaling(stls_handle h, int on);
+
+/*
  * s = P^{-1} r by Algorithm 1 steps 2-4 (§4.3): n-mode products with U^T
  * over every direction, division by lambda_t[i_t] + kappa^2 sum_k
  * lambda_k[i_k], n-mode products with U.  r, s: device, ndof doubles, may

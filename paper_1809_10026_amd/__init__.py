@@ -20,7 +20,7 @@ import numpy as np
 __all__ = [
     "LIB_PATH", "STLS_OK", "STLS_FD_FP64", "STLS_FD_FP32", "STLS_FD_BF16X3", "StlsError",
     "stls_setup", "stls_destroy", "stls_get_shape", "stls_get_factor", "stls_set_kappa",
-    "stls_set_fd_precision", "stls_prec_apply", "stls_matvec", "stls_pcg_solve",
+    "stls_set_fd_precision", "stls_set_fd_scaling", "stls_prec_apply", "stls_matvec", "stls_pcg_solve",
     "stls_pcg_history", "stls_set_profiling", "stls_profile", "stls_profile_reset",
     "Solver",
 ]
@@ -51,6 +51,7 @@ _sig = {
                                        ctypes.POINTER(ctypes.c_int64)]),
     "stls_set_kappa": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
     "stls_set_fd_precision": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "stls_set_fd_scaling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "stls_prec_apply": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
     "stls_matvec": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
     "stls_pcg_solve": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, ctypes.c_double, ctypes.c_int,
@@ -156,6 +157,10 @@ def stls_set_kappa(h, kappa):
 
 def stls_set_fd_precision(h, mode):
     _check(_lib.stls_set_fd_precision(h, int(mode)), "stls_set_fd_precision")
+
+
+def stls_set_fd_scaling(h, on):
+    _check(_lib.stls_set_fd_scaling(h, 1 if on else 0), "stls_set_fd_scaling")
 
 
 def stls_prec_apply(h, ndof, r, s):
@@ -365,6 +370,10 @@ class Solver:
 
     def set_fd_precision(self, mode):
         stls_set_fd_precision(self._h, mode)
+
+    def set_fd_scaling(self, on):
+        """Diagonally scaled preconditioner D^-1/2 P^-1 D^-1/2 (on) or P^-1 (off)."""
+        stls_set_fd_scaling(self._h, on)
 
     def factor(self, direction, what):
         return stls_get_factor(self._h, direction, what)

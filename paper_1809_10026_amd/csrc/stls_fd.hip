@@ -18,6 +18,7 @@
 
 #include <algorithm>
 
+#include "stls_diag.h"
 #include "stls_internal.h"
 
 namespace stls {
@@ -75,9 +76,13 @@ __device__ inline f4v mfma3(bf8_t ah, bf8_t al, bf8_t bh, bf8_t bl, f4v c) {
 // of the mode-2 product.  Y crosses waves through a double-buffered LDS tile
 // [j1][i2] of bf16 halves (one barrier per slab).  The next slab of X is
 // fetched into registers while the current one is processed.
+// SCALE: diagonal scaling of the preconditioner, sigma o x on the way in
+// (forward pass, TI = double) or sigma o z on the way out (backward pass),
+// sigma from the packed univariate diagonals staged in LDS (FP32).
 constexpr int kSlabLdy = 72;  // bf16 row stride of the Y tile (64 + 8)
+constexpr int kDiagLds = 3 * 3 * 64 + 2 * 64;  // packed diagonals, d = 3, n <= 64
 
-template <int NM, typename TI, typename TO, bool DOT>
+template <int NM, typename TI, typename TO, bool DOT, bool SCALE>
 __global__ __launch_bounds__(256) void fd_slab_bf16_kernel(const TI* __restrict__ X, TO* __restrict__ Z, int n1,
                                                            int n2, int nslab, const __bf16* __restrict__ W1h,
                                                            const __bf16* __restrict__ W1l,
@@ -85,14 +90,20 @@ __global__ __launch_bounds__(256) void fd_slab_bf16_kernel(const TI* __restrict_
                                                            const __bf16* __restrict__ W2l,
                                                            const double* __restrict__ dotv,
                                                            double* __restrict__ partials,
-                                                           const PcgScalars* __restrict__ gate) {
+                                                           const PcgScalars* __restrict__ gate, DiagScale S) {
   if (gate && (gate->done | gate->flag)) return;  // PCG already finished: nothing to do
   constexpr int NK = (NM + 1) / 2;
   constexpr int KPAD = NK * 32;
   constexpr int NP = NM * 16;
+  constexpr bool FWD = sizeof(TI) == 8;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __bf16* ytile = reinterpret_cast<__bf16*>(smem_raw);  // 2 buffers x {hi, lo} x [64][kSlabLdy]
   __shared__ double red[4];
+  __shared__ float dgs[SCALE ? kDiagLds : 1];
+  if constexpr (SCALE) {
+    for (int i = threadIdx.x; i < S.off[3] + 2 * S.n[3]; i += 256) dgs[i] = S.g32[i];
+    __syncthreads();
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, cl = lane & 15;
   bf8_t b1h[NM][NK], b1l[NM][NK], a2h[NK], a2l[NK];
@@ -147,11 +158,24 @@ __global__ __launch_bounds__(256) void fd_slab_bf16_kernel(const TI* __restrict_
           dv[nt * 4 + r] = dotv[base + (size_t)min(j2o + r, n2 - 1) * n1 + min(16 * nt + cl, n1 - 1)];
     }
     bf8_t xh[NK], xl[NK];
+    [[maybe_unused]] float sPm = 0.f, sPj = 0.f, sEk = 0.f, sEm = 0.f;
+    if constexpr (SCALE && FWD) {
+      const int idx[4] = {0, i2, sl % S.n[2], sl / S.n[2]};
+      diag_row_coeffs<float>(S, dgs, idx, sPm, sPj, sEk, sEm);
+    }
 #pragma unroll
     for (int kb = 0; kb < NK; ++kb) {
       float v[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = 32 * kb + 8 * g + e < n1 ? (float)px[kb][e] : 0.f;
+      for (int e = 0; e < 8; ++e) {
+        const int c = 32 * kb + 8 * g + e;
+        float x = (float)px[kb][e];
+        if constexpr (SCALE && FWD) {
+          const int cc = min(c, n1 - 1);
+          x *= diag_sigma(dgs[cc], dgs[n1 + cc], dgs[2 * n1 + cc], sPm, sPj, sEk, sEm);
+        }
+        v[e] = c < n1 ? x : 0.f;
+      }
       split8(v, xh[kb], xl[kb]);
     }
     fetch(min(sl + (int)gridDim.x, nslab - 1));  // always issued: uniform load order
@@ -177,6 +201,14 @@ __global__ __launch_bounds__(256) void fd_slab_bf16_kernel(const TI* __restrict_
     }
     __syncthreads();
     const __amdgpu_buffer_rsrc_t zr = buf_rsrc(Z + base, (size_t)ns * sizeof(TO));  // this slab of Z
+    [[maybe_unused]] float oPm[4], oPj[4], oEk[4], oEm[4];  // SCALE, backward: rows j2o + r
+    if constexpr (SCALE && !FWD) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int idx[4] = {0, min(j2o + r, n2 - 1), sl % S.n[2], sl / S.n[2]};
+        diag_row_coeffs<float>(S, dgs, idx, oPm[r], oPj[r], oEk[r], oEm[r]);
+      }
+    }
 #pragma unroll
     for (int nt = 0; nt < NM; ++nt) {
       f4v acc = f4v{0.f, 0.f, 0.f, 0.f};
@@ -186,10 +218,19 @@ __global__ __launch_bounds__(256) void fd_slab_bf16_kernel(const TI* __restrict_
         acc = mfma3(a2h[kb], a2l[kb], ld8(yh + o), ld8(yl + o), acc);
       }
       const int j1 = 16 * nt + cl;
+      [[maybe_unused]] float m1 = 0.f, k1 = 0.f, jj1 = 0.f;
+      if constexpr (SCALE && !FWD) {
+        const int cc = min(j1, n1 - 1);
+        m1 = dgs[cc];
+        k1 = dgs[n1 + cc];
+        jj1 = dgs[2 * n1 + cc];
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const bool ok = j1 < n1 && j2o + r < n2;
-        const TO zv = (TO)acc[r];
+        float zf = acc[r];
+        if constexpr (SCALE && !FWD) zf *= diag_sigma(m1, k1, jj1, oPm[r], oPj[r], oEk[r], oEm[r]);
+        const TO zv = (TO)zf;
         if constexpr (DOT) dsum += ok ? (double)zv * dv[nt * 4 + r] : 0.0;
         buf_store(zv, zr, ok ? (int)(((j2o + r) * n1 + j1) * sizeof(TO)) : kOutOfRange);
       }
@@ -362,7 +403,7 @@ __global__ __launch_bounds__(kStridedWaves * 64) void fd_strided_bf16_kernel(
   }
 }
 
-template <int NM, typename TI, typename TO, bool DOT>
+template <int NM, typename TI, typename TO, bool DOT, bool SCALE>
 int launch_slab(stls_ctx* h, const TI* X, TO* Z, bool fwd, const double* dotv, double* partials, int* nparts) {
   const DevDir& D1 = h->dd[0];
   const DevDir& D2 = h->dd[1];
@@ -376,8 +417,8 @@ int launch_slab(stls_ctx* h, const TI* X, TO* Z, bool fwd, const double* dotv, d
   const __bf16* W2h = (const __bf16*)(fwd ? D2.Hfwd : D2.Hbwd);
   const __bf16* W2l = (const __bf16*)(fwd ? D2.Lfwd : D2.Lbwd);
   prof_begin(h);
-  hipLaunchKernelGGL((fd_slab_bf16_kernel<NM, TI, TO, DOT>), dim3(blocks), dim3(256), shmem, h->stream, X, Z, n1, n2,
-                     nslab, W1h, W1l, W2h, W2l, dotv, partials, h->gate);
+  hipLaunchKernelGGL((fd_slab_bf16_kernel<NM, TI, TO, DOT, SCALE>), dim3(blocks), dim3(256), shmem, h->stream, X, Z,
+                     n1, n2, nslab, W1h, W1l, W2h, W2l, dotv, partials, h->gate, diag_scale_args(h));
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "fd_slab_bf16_kernel launch");
   prof_end(h, PROF_FD_SLAB);
@@ -419,13 +460,13 @@ int strided_nm(stls_ctx* h, const float* X, float* Y, int L, int k, bool fwd, co
   }
 }
 
-template <typename TI, typename TO, bool DOT>
+template <typename TI, typename TO, bool DOT, bool SCALE>
 int slab_nm(stls_ctx* h, const TI* X, TO* Z, bool fwd, const double* dotv, double* partials, int* nparts) {
   switch (h->dd[0].npad / 16) {
-    case 1: return launch_slab<1, TI, TO, DOT>(h, X, Z, fwd, dotv, partials, nparts);
-    case 2: return launch_slab<2, TI, TO, DOT>(h, X, Z, fwd, dotv, partials, nparts);
-    case 3: return launch_slab<3, TI, TO, DOT>(h, X, Z, fwd, dotv, partials, nparts);
-    case 4: return launch_slab<4, TI, TO, DOT>(h, X, Z, fwd, dotv, partials, nparts);
+    case 1: return launch_slab<1, TI, TO, DOT, SCALE>(h, X, Z, fwd, dotv, partials, nparts);
+    case 2: return launch_slab<2, TI, TO, DOT, SCALE>(h, X, Z, fwd, dotv, partials, nparts);
+    case 3: return launch_slab<3, TI, TO, DOT, SCALE>(h, X, Z, fwd, dotv, partials, nparts);
+    case 4: return launch_slab<4, TI, TO, DOT, SCALE>(h, X, Z, fwd, dotv, partials, nparts);
     default: set_error("direction too large for the slab bf16 pass"); return STLS_EINVAL;
   }
 }
@@ -443,20 +484,27 @@ bool fd_bf16_five_pass_covers(const stls_ctx* h) {
   return h->ndof * (int64_t)sizeof(float) < ((int64_t)1 << 31) - 1;
 }
 
-int prec_apply_bf16x3_five_pass(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
-                                int* nparts) {
+template <bool SCALE>
+static int five_pass(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
+                     int* nparts) {
   float* b0 = reinterpret_cast<float*>(h->fdbuf[0]);
   float* b1 = reinterpret_cast<float*>(h->fdbuf[1]);
   const int n1 = h->dir[0].n, n2 = h->dir[1].n;
   const int L3 = n1 * n2;
   const int ns = (int)h->ns;
   int st;
-  if ((st = slab_nm<double, float, false>(h, r, b0, true, nullptr, nullptr, nullptr))) return st;
+  if ((st = slab_nm<double, float, false, SCALE>(h, r, b0, true, nullptr, nullptr, nullptr))) return st;
   if ((st = strided_nm<false>(h, b0, b1, L3, 2, true, nullptr))) return st;
   if ((st = strided_nm<true>(h, b1, b0, ns, 3, true, h->dd[3].lam))) return st;
   if ((st = strided_nm<false>(h, b0, b1, L3, 2, false, nullptr))) return st;
-  if (dot_with) return slab_nm<float, double, true>(h, b1, s, false, dot_with, partials, nparts);
-  return slab_nm<float, double, false>(h, b1, s, false, nullptr, nullptr, nparts);
+  if (dot_with) return slab_nm<float, double, true, SCALE>(h, b1, s, false, dot_with, partials, nparts);
+  return slab_nm<float, double, false, SCALE>(h, b1, s, false, nullptr, nullptr, nparts);
+}
+
+int prec_apply_bf16x3_five_pass(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
+                                int* nparts, bool scale) {
+  return scale ? five_pass<true>(h, r, s, dot_with, partials, nparts)
+               : five_pass<false>(h, r, s, dot_with, partials, nparts);
 }
 
 }  // namespace stls

@@ -431,6 +431,45 @@ static int upload_lambda_s(stls_ctx* h) {
   return STLS_OK;
 }
 
+// Packed univariate diagonals for the diagonal scaling of the FD
+// preconditioner (DiagScale layout): [m_k | k_k | j_k] per space direction,
+// then [k_t | m_t]; the band's diagonal is its column p.
+static int upload_diagonals(stls_ctx* h) {
+  std::vector<double> g;
+  for (int k = 0; k <= h->d; ++k) {
+    const Dir& D = h->dir[k];
+    const size_t bw = 2 * (size_t)D.p + 1;
+    const std::vector<double>* bands[3] = {&D.M, &D.K, &D.J};
+    if (D.is_time) { bands[0] = &D.K; bands[1] = &D.M; }
+    for (int b = 0; b < (D.is_time ? 2 : 3); ++b)
+      for (int i = 0; i < D.n; ++i) g.push_back((*bands[b])[(size_t)i * bw + (size_t)D.p]);
+  }
+  std::vector<float> g32(g.begin(), g.end());
+  int st = dev_upload(&h->diag64, g.data(), g.size(), h->stream);
+  if (!st) st = dev_upload(&h->diag32, g32.data(), g32.size(), h->stream);
+  if (st) return st;
+  const hipError_t e = hipStreamSynchronize(h->stream);  // the host vectors go out of scope
+  return e == hipSuccess ? STLS_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+DiagScale diag_scale_args(const stls_ctx* h) {
+  DiagScale S;
+  S.g = h->diag64;
+  S.g32 = h->diag32;
+  S.d = h->d;
+  int off = 0;
+  for (int k = 0; k < h->d; ++k) {
+    S.n[k] = h->dir[k].n;
+    S.off[k] = off;
+    off += 3 * S.n[k];
+  }
+  S.n[h->d] = h->dir[h->d].n;
+  S.off[h->d] = off;
+  S.k2 = h->kappa * h->kappa;
+  S.kw = h->kappa * h->dir[h->d].wend;
+  return S;
+}
+
 int ensure_diff_operands(stls_ctx* h) {
   if (h->diff_ready) return STLS_OK;
   int st = STLS_OK;
@@ -462,7 +501,7 @@ static void free_ctx(stls_ctx* h) {
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
   }
-  void* ptrs[] = {h->lam_s, h->lam_s_raw, h->work[0], h->work[1], h->work[2], h->work[3], h->work[4],
+  void* ptrs[] = {h->diag64, h->diag32, h->lam_s, h->lam_s_raw, h->work[0], h->work[1], h->work[2], h->work[3], h->work[4],
                   h->work[5], h->fdbuf[0], h->fdbuf[1], h->r, h->z, h->pvec, h->q, h->partials, h->scal,
                   h->dres, h->ftmp[0], h->ftmp[1]};
   for (void* p : ptrs)
@@ -561,6 +600,7 @@ int stls_setup(int d, const int* nknots, const double* const* knots, const int* 
     if (!st) st = upload_fd_operands(h, k);
   }
   if (!st) st = upload_lambda_s(h);
+  if (!st) st = upload_diagonals(h);
   const size_t nb = (size_t)h->ndof * sizeof(double);
   auto alloc = [&](double** p, size_t bytes) {
     if (st) return;
@@ -570,7 +610,7 @@ int stls_setup(int d, const int* nknots, const double* const* knots, const int* 
       st = e == hipErrorOutOfMemory ? STLS_ENOMEM : STLS_EHIP;
     }
   };
-  const int nwork = d == 1 ? 0 : 3;
+  const int nwork = d == 1 ? 1 : 3;  // matvec intermediates (d >= 2); the scaled FD's input copy
   for (int i = 0; i < nwork; ++i) alloc(&h->work[i], nb);
   alloc(&h->fdbuf[0], nb);
   alloc(&h->fdbuf[1], nb);
@@ -648,6 +688,12 @@ int stls_set_kappa(stls_handle h, double kappa) {
 int stls_set_fd_precision(stls_handle h, int mode) {
   if (!h || mode < STLS_FD_FP64 || mode > STLS_FD_BF16X3) { set_error("bad handle or precision mode"); return STLS_EINVAL; }
   h->fd_mode = mode;
+  return STLS_OK;
+}
+
+int stls_set_fd_scaling(stls_handle h, int on) {
+  if (!h) { set_error("NULL handle"); return STLS_EINVAL; }
+  h->fd_scale = on != 0;
   return STLS_OK;
 }
 

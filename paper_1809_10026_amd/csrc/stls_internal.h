@@ -69,6 +69,20 @@ struct PcgScalars {
   int pad;
 };
 
+// Arguments of the diagonal scaling of the FD preconditioner (§4.4, closing
+// definition): D_ii = A_ii / P_ii from the univariate diagonals, packed per
+// space direction k as [m_k | k_k | j_k] (n_k entries each, diagonals of the
+// restricted M, K, J) at off[k], and for time as [k_t | m_t] at off[d].
+struct DiagScale {
+  const double* g = nullptr;  // packed diagonals, FP64
+  const float* g32 = nullptr; // the same, FP32
+  int d = 0;
+  int n[kMaxDim + 1] = {0, 0, 0, 0};
+  int off[kMaxDim + 1] = {0, 0, 0, 0};
+  double k2 = 1.0;  // kappa^2
+  double kw = 0.0;  // kappa times the single entry of W_t (final time)
+};
+
 enum ProfId {
   PROF_FD_SPACE = 0,  // dense n-mode product over one space direction
   PROF_FD_TIME,       // fused time-mode forward product / division / backward product
@@ -91,6 +105,9 @@ struct stls_ctx {
   double kappa = 1.0;
   hipStream_t stream = nullptr;
   int fd_mode = STLS_FD_FP64;
+  bool fd_scale = false;     // diagonal scaling D^-1/2 P^-1 D^-1/2 (stls_set_fd_scaling)
+  double* diag64 = nullptr;  // packed univariate diagonals (DiagScale layout)
+  float* diag32 = nullptr;
   stls::Dir dir[stls::kMaxDim + 1];
   stls::DevDir dd[stls::kMaxDim + 1];
   int64_t ndof = 0, ns = 0;  // ns = spatial dofs
@@ -145,10 +162,11 @@ int launch_matvec(stls_ctx* h, const double* x, double* y, const double* dot_wit
 int pcg_run(stls_ctx* h, const double* b, double* x, double rtol, int maxit, int* iters,
             double* relres);
 int upload_fd_operands(stls_ctx* h, int k);
+DiagScale diag_scale_args(const stls_ctx* h);
 // Five-pass BF16x3 FD chain for d = 3 (stls_fd.hip).
 bool fd_bf16_five_pass_covers(const stls_ctx* h);
 int prec_apply_bf16x3_five_pass(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
-                                int* nparts);
+                                int* nparts, bool scale);
 int ensure_diff_operands(stls_ctx* h);
 
 // profiling helpers

@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <vector>
 
+#include "stls_diag.h"
 #include "stls_internal.h"
 
 namespace stls {
@@ -658,16 +659,82 @@ static int prec_apply_t(stls_ctx* h, const double* r, double* s, const double* d
   return STLS_OK;
 }
 
-int launch_prec_apply(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
-                      int* nparts) {
+// Diagonal scaling around the FD chains (§4.4, closing definition):
+// y_i = sigma_i x_i with sigma_i = (P_ii / A_ii)^1/2 in FP64, the multi-index
+// decoded from the colex position; optional partial sums of y . dotv (one
+// per block).  x and y may alias.
+constexpr int kScaleBlocks = 2048;
+template <bool DOT>
+__global__ __launch_bounds__(kThreads) void diag_scale_kernel(const double* x, double* y, int64_t n, DiagScale S,
+                                                              const double* __restrict__ dotv,
+                                                              double* __restrict__ partials,
+                                                              const PcgScalars* __restrict__ gate) {
+  if (gate && (gate->done | gate->flag)) return;  // PCG already finished: nothing to do
+  __shared__ double red[kThreads / 64];
+  double dsum = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    int idx[kMaxDim + 1];
+    int64_t rest = i;
+#pragma unroll
+    for (int k = 0; k <= kMaxDim; ++k) {
+      if (k > S.d) break;
+      idx[k] = (int)(rest % S.n[k]);
+      rest /= S.n[k];
+    }
+    double Pm, Pj, Ek, Em;
+    diag_row_coeffs<double>(S, S.g, idx, Pm, Pj, Ek, Em);
+    const double* g1 = S.g + S.off[0];
+    const int i1 = idx[0];
+    const double v = diag_sigma(g1[i1], g1[S.n[0] + i1], g1[2 * S.n[0] + i1], Pm, Pj, Ek, Em) * x[i];
+    y[i] = v;
+    if constexpr (DOT) dsum += v * dotv[i];
+  }
+  if constexpr (DOT) {
+    const double t = block_sum(dsum, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  }
+}
+
+static int launch_diag_scale(stls_ctx* h, const double* x, double* y, const double* dot_with, double* partials,
+                             int* nparts) {
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((h->ndof + kThreads - 1) / kThreads, kScaleBlocks));
+  const DiagScale S = diag_scale_args(h);
+  prof_begin(h);
+  if (dot_with)
+    hipLaunchKernelGGL(diag_scale_kernel<true>, dim3(blocks), dim3(kThreads), 0, h->stream, x, y, h->ndof, S,
+                       dot_with, partials, h->gate);
+  else
+    hipLaunchKernelGGL(diag_scale_kernel<false>, dim3(blocks), dim3(kThreads), 0, h->stream, x, y, h->ndof, S,
+                       nullptr, nullptr, h->gate);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "diag_scale_kernel launch");
+  prof_end(h, PROF_VEC);
+  if (nparts) *nparts = blocks;
+  return STLS_OK;
+}
+
+static int prec_apply_plain(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
+                            int* nparts) {
   switch (h->fd_mode) {
     case STLS_FD_FP64: return prec_apply_t<double>(h, r, s, dot_with, partials, nparts);
     case STLS_FD_FP32: return prec_apply_t<float>(h, r, s, dot_with, partials, nparts);
-    case STLS_FD_BF16X3:
-      if (fd_bf16_five_pass_covers(h)) return prec_apply_bf16x3_five_pass(h, r, s, dot_with, partials, nparts);
-      return prec_apply_bf16x3(h, r, s, dot_with, partials, nparts);
+    case STLS_FD_BF16X3: return prec_apply_bf16x3(h, r, s, dot_with, partials, nparts);
     default: set_error("FD precision mode not available"); return STLS_EINVAL;
   }
+}
+
+int launch_prec_apply(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
+                      int* nparts) {
+  if (h->fd_mode == STLS_FD_BF16X3 && fd_bf16_five_pass_covers(h))
+    return prec_apply_bf16x3_five_pass(h, r, s, dot_with, partials, nparts, h->fd_scale);  // scaling fused
+  if (!h->fd_scale) return prec_apply_plain(h, r, s, dot_with, partials, nparts);
+  // scaled: sigma o r into a matvec intermediate (free while the FD runs),
+  // the chain, then sigma o s in place with the dot product
+  double* tmp = h->work[0];
+  int st = launch_diag_scale(h, r, tmp, nullptr, nullptr, nullptr);
+  if (!st) st = prec_apply_plain(h, tmp, s, nullptr, nullptr, nullptr);
+  if (!st) st = launch_diag_scale(h, s, s, dot_with, partials, nparts);
+  return st;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,118 @@
+"""Parity at the benchmark workload's full size, in the launch configuration
+the benchmark times: d = 3, p = 4, 48 elements per direction, N = 6,375,000,
+right-hand side U[-1, 1] with the benchmark's seed.
+
+The oracle applies the matvec and the FD preconditioner to the whole vector
+in a few seconds, so those are compared entry by entry; a full oracle PCG
+would take about a minute, so the solves are checked by properties that hold
+at any size: the oracle's matvec gives the true residual of the GPU solution,
+and the solutions of the different FD precisions agree to the solve
+tolerance.  Tolerances as in the small-size parity tests.
+"""
+import numpy as np
+import pytest
+
+from stls_inputs import CONFIGS, problem_knots, uniform_pm1
+
+pytestmark = pytest.mark.gpu
+
+try:
+    import paper_1809_10026_amd as stls
+except ImportError:  # library not built: GPU tests must fail loudly, not skip
+    stls = None
+
+from oracle import fd as ofd, system as osys  # noqa: E402
+from tests.gpu_util import rel_err, to_dev, to_host  # noqa: E402
+
+CFG = CONFIGS["d3_p4_nel48"]
+
+
+@pytest.fixture(scope="module")
+def full():
+    assert stls is not None, "libstls.so is not built; run python paper_1809_10026_amd/build.py"
+    knots, degs = problem_knots(CFG["d"], CFG["n_el"], CFG["p"])
+    S = stls.Solver(knots, degs)
+    P = osys.Problem(knots, degs)
+    F = ofd.FD(P)
+    return S, P, F
+
+
+def test_fullsize_shape(full):
+    S, P, _ = full
+    assert S.shape == P.shape == (50, 50, 50, 51) and S.ndof == 6375000
+
+
+def test_fullsize_matvec(full):
+    S, P, _ = full
+    x = uniform_pm1(S.ndof, 41)
+    assert rel_err(to_host(S.matvec(to_dev(x))), osys.vec(P.matvec(x))) < 1e-13
+
+
+def _eig_bounds(P):
+    """Every term of P is a Kronecker product of symmetric positive
+    semidefinite factors, whose eigenvalues are the products of the factors'
+    eigenvalues: lambda_max(P) <= sum c prod max, lambda_min(P) >= sum c prod min."""
+    hi = sum(c * np.prod([np.linalg.eigvalsh(W).max() for W in f]) for c, f in P.prec_terms())
+    lo = sum(c * np.prod([np.linalg.eigvalsh(W).min() for W in f]) for c, f in P.prec_terms())
+    return hi, lo
+
+
+@pytest.mark.parametrize("mode,scaled,tol", [(0, False, None), (1, False, 2e-5), (2, False, 5e-4),
+                                             (0, True, None), (2, True, 5e-4)])
+def test_fullsize_prec_apply(full, mode, scaled, tol):
+    """FP64: the backward error ||P s - r|| / (||P|| ||s||) is at rounding
+    level (||P|| bounded above through the factors' eigenvalues), and the
+    difference to the oracle is within 10 eps cond(P) (cond(P) <= 7e11 here:
+    the forward difference of two backward-stable solves can be that large,
+    so the backward error is the sharp check).  FP32 / BF16x3: the product
+    error bounds of the small-size tests."""
+    S, P, F = full
+    S.set_fd_precision(mode)
+    S.set_fd_scaling(scaled)
+    try:
+        r = uniform_pm1(S.ndof, 42)
+        s = to_host(S.prec_apply(to_dev(r)))
+        G = ofd.ScaledFD(P, F) if scaled else None
+        ref = osys.vec(G.apply(r) if scaled else F.apply(r))
+        if tol is not None:
+            assert rel_err(s, ref) < tol
+            return
+        hi, lo = _eig_bounds(P)
+        if scaled:  # P^G = D^1/2 P D^1/2
+            sq = osys.vec(np.sqrt(G.D))
+            Ps = sq * osys.vec(P.prec_matvec(sq * s))
+            hi, lo = hi * G.D.max(), lo * G.D.min()
+        else:
+            Ps = osys.vec(P.prec_matvec(s))
+        backward = np.linalg.norm(Ps - r) / (hi * np.linalg.norm(s))
+        print(f"backward {backward:.2e} forward {rel_err(s, ref):.2e} cond bound {hi / lo:.2e}", flush=True)
+        assert backward < 1e-14
+        assert rel_err(s, ref) < max(1e-12, 10 * np.finfo(float).eps * hi / lo)
+    finally:
+        S.set_fd_precision(0)
+        S.set_fd_scaling(False)
+
+
+def test_fullsize_pcg(full):
+    """The benchmark's solve in every mode: true residual by the oracle's
+    matvec, and agreement with the FP64 solution."""
+    S, P, _ = full
+    b = uniform_pm1(S.ndof, CFG["seed"])
+    bd = to_dev(b)
+    sols = {}
+    try:
+        for mode, scaled in [(0, False), (1, False), (2, False), (2, True)]:
+            S.set_fd_precision(mode)
+            S.set_fd_scaling(scaled)
+            x, it, rel = S.solve(bd, rtol=CFG["rtol"], maxit=200)
+            xo = to_host(x)
+            true_rel = np.linalg.norm(b - osys.vec(P.matvec(xo))) / np.linalg.norm(b)
+            print(f"mode {mode} scaled {scaled}: {it} iterations, relres {rel:.2e}, true {true_rel:.2e}", flush=True)
+            assert rel <= CFG["rtol"] and true_rel < 2 * CFG["rtol"]
+            sols[(mode, scaled)] = xo
+    finally:
+        S.set_fd_precision(0)
+        S.set_fd_scaling(False)
+    ref = sols[(0, False)]
+    for key, xo in sols.items():
+        assert rel_err(xo, ref) < 2 * 3 * 10 * CFG["rtol"], key
