@@ -146,6 +146,34 @@ int stls_matvec(stls_handle h, const double* x, double* y);
 int stls_pcg_solve(stls_handle h, const double* b, double* x, double rtol, int maxit,
                    int* iters, double* relres);
 
+/*
+ * Quadrature grid of the error norms (§5.1: element-wise Gauss quadrature,
+ * p + 3 points per non-empty knot span of the direction).
+ *  dir    0..d-1 space directions, d time.
+ *  x, w   host buffers of *nq doubles for the points and weights, or both
+ *         NULL to query *nq only.
+ */
+int stls_norm_points(stls_handle h, int dir, double* x, double* w, int* nq);
+
+/*
+ * Relative errors of u_h = sum_i u_i B_i against an exact solution given as
+ * a sum of separable terms u(x, t) = sum_s prod_k g_{s,k}(x_k) (§3.1
+ * eq. norm_V0, §5.1):
+ *   out[0] = ||u - u_h||_V0 / ||u||_V0 with ||v||_V0^2 = int int (d_t v)^2 + (Lap v)^2,
+ *   out[1] = L^2 relative error,
+ *   out[2] = relative error in the space-time H^1 norm (v, d_t v, grad_x v).
+ *  u       device, ndof doubles: the coefficients (colex).
+ *  nterms  1..64.
+ *  g       host array of nterms*(d+1) host pointers; g[s*(d+1)+k] holds
+ *          3*nq_k doubles: g_{s,k}, g_{s,k}' and g_{s,k}'' at the points of
+ *          stls_norm_points(h, k, ...), in that order.
+ *  out     host, 3 doubles.
+ * Device temporaries (about 3 * prod_k nq_k(space) * n_t doubles) are
+ * allocated for the call and freed before it returns; synchronises the
+ * stream.  STLS_ENOMEM if they do not fit.
+ */
+int stls_error_norms(stls_handle h, const double* u, int nterms, const double* const* g, double* out);
+
 /* Residual history of the last stls_pcg_solve: out[k] = ||r_k||/||b||,
  * k = 0..iters (host buffer of at least max entries); *count = iters + 1. */
 int stls_pcg_history(stls_handle h, double* out, int max, int* count);

@@ -21,7 +21,7 @@ __all__ = [
     "LIB_PATH", "STLS_OK", "STLS_FD_FP64", "STLS_FD_FP32", "STLS_FD_BF16X3", "StlsError",
     "stls_setup", "stls_destroy", "stls_get_shape", "stls_get_factor", "stls_set_kappa",
     "stls_set_fd_precision", "stls_set_fd_scaling", "stls_prec_apply", "stls_matvec", "stls_pcg_solve",
-    "stls_pcg_history", "stls_set_profiling", "stls_profile", "stls_profile_reset",
+    "stls_pcg_history", "stls_norm_points", "stls_error_norms", "stls_set_profiling", "stls_profile", "stls_profile_reset",
     "Solver",
 ]
 
@@ -57,6 +57,8 @@ _sig = {
     "stls_pcg_solve": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, ctypes.c_double, ctypes.c_int,
                                       _c_int_p, ctypes.POINTER(ctypes.c_double)]),
     "stls_pcg_history": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, _c_int_p]),
+    "stls_norm_points": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, _c_int_p]),
+    "stls_error_norms": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "stls_set_profiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "stls_profile_count": (ctypes.c_int, []),
     "stls_profile_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
@@ -178,6 +180,27 @@ def stls_pcg_solve(h, ndof, b, x, rtol, maxit, raise_on_noconv=True):
     st = _check(_lib.stls_pcg_solve(h, _dev_ptr(b, ndof, "b"), _dev_ptr(x, ndof, "x"), float(rtol), int(maxit),
                                     ctypes.byref(it), ctypes.byref(rel)), "stls_pcg_solve", ok)
     return int(it.value), float(rel.value), st
+
+
+def stls_norm_points(h, direction):
+    """Quadrature points and weights of the error norms in one direction."""
+    nq = ctypes.c_int()
+    _check(_lib.stls_norm_points(h, int(direction), None, None, ctypes.byref(nq)), "stls_norm_points")
+    x, w = np.zeros(nq.value), np.zeros(nq.value)
+    _check(_lib.stls_norm_points(h, int(direction), x.ctypes.data, w.ctypes.data, ctypes.byref(nq)),
+           "stls_norm_points")
+    return x, w
+
+
+def stls_error_norms(h, ndof, u, factors):
+    """factors[s][k]: array (3, nq_k) of g_{s,k}, g', g'' at the direction's
+    norm points; returns the relative V0, L2 and H1 errors."""
+    arrays = [np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(-1)) for term in factors for f in term]
+    ptrs = (ctypes.c_void_p * len(arrays))(*[a.ctypes.data for a in arrays])
+    out = np.zeros(3)
+    _check(_lib.stls_error_norms(h, _dev_ptr(u, ndof, "u"), len(factors), ptrs, out.ctypes.data),
+           "stls_error_norms")
+    return dict(V0=float(out[0]), L2=float(out[1]), H1=float(out[2]))
 
 
 def stls_pcg_history(h):
@@ -395,6 +418,14 @@ class Solver:
 
     def history(self):
         return stls_pcg_history(self._h)
+
+    def norm_points(self, direction):
+        return stls_norm_points(self._h, direction)
+
+    def error_norms(self, u, factors):
+        """Relative V0 / L2 / H1 errors of u against sum_s prod_k g_{s,k}
+        (factors[s][k] = (g, g', g'') at norm_points(k))."""
+        return stls_error_norms(self._h, self.ndof, u, factors)
 
     # --- differentiation operators ---------------------------------------
     @property

@@ -42,7 +42,7 @@ static void legendre_eval(int q, double z, double& pq, double& dpq) {
   dpq = q * (z * pk - pkm1) / (z * z - 1.0);  // P_q'(z) from P_q and P_{q-1}
 }
 
-static void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w) {
+void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w) {
   x.assign(q, 0.0);
   w.assign(q, 0.0);
   const double pi = 3.14159265358979323846;
@@ -72,7 +72,7 @@ static void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w
 // N_{s-p+a,p}(u), k = 0..2.
 static inline double ratio(double num, double den) { return den == 0.0 ? 0.0 : num / den; }
 
-static void span_basis(const std::vector<double>& xi, int p, int s, double u, double v[3][16]) {
+void span_basis(const std::vector<double>& xi, int p, int s, double u, double v[3][16]) {
   // tab[q][a] = N_{s-q+a, q}(u)
   double tab[16][16];
   tab[0][0] = 1.0;

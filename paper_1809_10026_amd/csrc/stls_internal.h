@@ -153,6 +153,11 @@ int validate_and_build_dir(const double* knots, int nknots, int p, bool is_time,
                            std::string& err);
 void sym_generalized_eig(int n, const std::vector<double>& Kdense, const std::vector<double>& Mdense,
                          std::vector<double>& U, std::vector<double>& lam);
+// Gauss-Legendre nodes and weights on [-1, 1] (q <= 16)
+void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w);
+// values and first two derivatives of the p+1 B-splines nonzero on the
+// non-empty span s at u: v[k][a] = d^k/du^k N_{s-p+a,p}(u)
+void span_basis(const std::vector<double>& xi, int p, int s, double u, double v[3][16]);
 
 // kernel launchers (stls_kernels.hip)
 int launch_prec_apply(stls_ctx* h, const double* r, double* s, const double* dot_with,
