@@ -196,9 +196,12 @@ def main():
                     traffic_unit="MB per launch", algorithmic_MB_per_launch=round(dom["bytes_per_launch"] / 1e6, 3),
                     avg_us=round(dom["avg_us"], 3))
 
+    err_norms = gpu_error_norms(stls, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(knots, degs, b.cpu().numpy(), res["fp64"]["iters"], N)
+        err_norms["oracle_cpu"] = cpu_error_norms()
 
     t_mixed, t_fp64 = res[mixed]["time_s"], res["fp64"]["time_s"]
     out = {
@@ -226,6 +229,7 @@ def main():
         "fd_prec_dof_per_s": {k: N / v["fd_apply_s"] for k, v in res.items()},
         "matvec_dof_per_s": N / mv_s,
         "diag_scaled_prec": scaled,
+        "error_norms": err_norms,
         "setup_s": setup_s,
         "roofline": roofline,
         "roofline_note": "kernel durations from HIP events recorded around every launch on the solver's "
@@ -234,6 +238,64 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def _sin_factors(x):
+    import numpy as np
+    pi = np.pi
+    return np.stack([np.sin(pi * x), pi * np.cos(pi * x), -pi * pi * np.sin(pi * x)])
+
+
+def gpu_error_norms(stls, torch, reps=3):
+    """Error norms (§5.1) on the GPU: V0, L2 and H1 errors of a d = 2, p = 3,
+    64-element solution (right-hand side U[-1, 1], seed 1809) against
+    u = sin(pi x) sin(pi y) sin(pi t), timed per evaluation."""
+    import numpy as np
+
+    from stls_inputs import CONFIGS, problem_knots, uniform_pm1
+    c = CONFIGS["d2_p3_nel64"]
+    S = stls.Solver(*problem_knots(c["d"], c["n_el"], c["p"]))
+    b = torch.as_tensor(uniform_pm1(S.ndof, c["seed"])).cuda()
+    x, _, _ = S.solve(b, c["rtol"], 300)
+    pts = [S.norm_points(k)[0] for k in range(c["d"] + 1)]
+    fac = [[_sin_factors(p) for p in pts]]
+    S.error_norms(x, fac)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        res = S.error_norms(x, fac)
+    dt = (time.perf_counter() - t) / reps
+    grid = int(np.prod([len(p) for p in pts]))
+    log(f"error norms: {dt*1e3:.1f} ms for {grid} grid points")
+    return {"workload": "d=2, p=3, 64 elements/dir (N=278,850), u_h solved from a U[-1,1] RHS (seed 1809), "
+                        "exact u = sin(pi x) sin(pi y) sin(pi t), p+3 Gauss points per span",
+            "seconds": dt, "grid_points": grid, "fields": 2 * c["d"] + 2, "grid_points_per_s": grid / dt,
+            "norms": res}
+
+
+def cpu_error_norms(nel=32):
+    """The oracle's error norms (numpy, host cores) on the same kind of
+    workload at 32 elements per direction (7.1 M grid points)."""
+    import numpy as np
+
+    from oracle import norms, system
+    from stls_inputs import problem_knots, uniform_pm1
+    pi = np.pi
+    ex = dict(u=lambda x, y, t: np.sin(pi * x) * np.sin(pi * y) * np.sin(pi * t),
+              ut=lambda x, y, t: np.sin(pi * x) * np.sin(pi * y) * pi * np.cos(pi * t),
+              lap=lambda x, y, t: -2 * pi * pi * np.sin(pi * x) * np.sin(pi * y) * np.sin(pi * t),
+              grad=[lambda x, y, t: pi * np.cos(pi * x) * np.sin(pi * y) * np.sin(pi * t),
+                    lambda x, y, t: pi * np.sin(pi * x) * np.cos(pi * y) * np.sin(pi * t)])
+    knots, degs = problem_knots(2, nel, 3)
+    P = system.Problem(knots, degs)
+    u = uniform_pm1(P.ndof, 1809)
+    t = time.perf_counter()
+    norms.error_norms(system.unvec(u, P.shape), knots, degs, ex)
+    dt = time.perf_counter() - t
+    grid = (nel * 6) ** 3
+    log(f"cpu error norms: {dt:.2f} s for {grid} grid points")
+    return {"kind": "oracle", "workload": f"d=2, p=3, {nel} elements/dir", "seconds": dt, "grid_points": grid,
+            "grid_points_per_s": grid / dt}
 
 
 def cpu_baseline(knots, degs, b, iters_fp64, N, sample_its=3):
