@@ -253,12 +253,14 @@ __global__ __launch_bounds__(256) void fd_slab_bf16_kernel(const TI* __restrict_
 // no copy of an in-flight value forces an early wait).  FUSED: time mode,
 //   Q(i, c) = (W X)(i, c) / (lambda_t[i] + lambda_s[c])  (FP32 quotient),
 //   Y = W2 Q,
-// with Q re-fragmented through a per-wave LDS scratch tile.
+// with Q re-fragmented through a per-wave LDS scratch tile.  WL: the
+// forward operator's fragments are read from LDS at each product instead of
+// being held in registers (fewer registers, more waves per CU).
 constexpr int kStridedWaves = 8;
 constexpr int kStridedDepth = 2;
 
-template <int NM, bool FUSED>
-__global__ __launch_bounds__(kStridedWaves * 64) void fd_strided_bf16_kernel(
+template <int NM, bool FUSED, bool WL>
+__global__ __launch_bounds__(kStridedWaves * 64, (WL && !FUSED) ? 4 : 2) void fd_strided_bf16_kernel(
     const float* __restrict__ X, float* __restrict__ Y, int L, int n, int ncols, const __bf16* __restrict__ Wh,
     const __bf16* __restrict__ Wl, const __bf16* __restrict__ W2h, const __bf16* __restrict__ W2l,
     const double* __restrict__ lam_t, const double* __restrict__ lam_s, const PcgScalars* __restrict__ gate) {
@@ -270,21 +272,31 @@ __global__ __launch_bounds__(kStridedWaves * 64) void fd_strided_bf16_kernel(
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, cl = lane & 15;
-  // fused kernel LDS: lambda_t (16 NM doubles, clamped), the backward
-  // operator's bf16 halves [16 NM][KPAD + 8] (registers hold the forward one),
-  // then the per-wave scratch tiles
+  // LDS: (fused) lambda_t (16 NM doubles, clamped) and the backward
+  // operator's bf16 halves [16 NM][KPAD + 8]; (WL) the forward operator's
+  // halves, same layout; (fused) the per-wave scratch tiles
   constexpr int LDV = KPAD + 8;
+  constexpr int kOpBytes = 2 * 16 * NM * LDV * 2;
   double* lt_lds = reinterpret_cast<double*>(smem_raw);
   __bf16* v2h = reinterpret_cast<__bf16*>(smem_raw + 16 * NM * sizeof(double));
   __bf16* v2l = v2h + 16 * NM * LDV;
-  float* myscr = reinterpret_cast<float*>(smem_raw + (FUSED ? 16 * NM * sizeof(double) + 2 * 16 * NM * LDV * 2 : 0)) +
-                 wave * 16 * LDS_S;
-  if constexpr (FUSED) {
-    for (int i = threadIdx.x; i < 16 * NM; i += blockDim.x) lt_lds[i] = lam_t[min(i, n - 1)];
+  unsigned char* after_fused = smem_raw + (FUSED ? 16 * NM * sizeof(double) + kOpBytes : 0);
+  __bf16* w1h = reinterpret_cast<__bf16*>(after_fused);
+  __bf16* w1l = w1h + 16 * NM * LDV;
+  float* myscr = reinterpret_cast<float*>(after_fused + (WL ? kOpBytes : 0)) + wave * 16 * LDS_S;
+  if constexpr (FUSED || WL) {
+    if constexpr (FUSED)
+      for (int i = threadIdx.x; i < 16 * NM; i += blockDim.x) lt_lds[i] = lam_t[min(i, n - 1)];
     for (int e = threadIdx.x; e < 16 * NM * KPAD; e += blockDim.x) {
       const int i = e / KPAD, k = e - i * KPAD;
-      v2h[i * LDV + k] = W2h[e];
-      v2l[i * LDV + k] = W2l[e];
+      if constexpr (FUSED) {
+        v2h[i * LDV + k] = W2h[e];
+        v2l[i * LDV + k] = W2l[e];
+      }
+      if constexpr (WL) {
+        w1h[i * LDV + k] = Wh[e];
+        w1l[i * LDV + k] = Wl[e];
+      }
     }
     __syncthreads();
   }
@@ -292,20 +304,22 @@ __global__ __launch_bounds__(kStridedWaves * 64) void fd_strided_bf16_kernel(
   const int stride = gridDim.x * kStridedWaves;
   const int u0 = blockIdx.x * kStridedWaves + wave;
   if (u0 >= nunits) return;
-  bf8_t wh[NM][NK], wl[NM][NK];
+  bf8_t wh[WL ? 1 : NM][NK], wl[WL ? 1 : NM][NK];
+  if constexpr (!WL) {
 #pragma unroll
-  for (int t = 0; t < NM; ++t)
+    for (int t = 0; t < NM; ++t)
 #pragma unroll
-    for (int kb = 0; kb < NK; ++kb) {
-      const int off = (16 * t + cl) * KPAD + 32 * kb + 8 * g;
-      wh[t][kb] = ld8(Wh + off);
-      wl[t][kb] = ld8(Wl + off);
-    }
-  // the operator fragments arrive before the column prefetch is issued:
-  // were they queued behind it, the loop's waits (taken over the entry path
-  // as well) would drain the whole prefetch on every unit
-  __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8));  // vmcnt(0)
-  __builtin_amdgcn_sched_barrier(0);
+      for (int kb = 0; kb < NK; ++kb) {
+        const int off = (16 * t + cl) * KPAD + 32 * kb + 8 * g;
+        wh[t][kb] = ld8(Wh + off);
+        wl[t][kb] = ld8(Wl + off);
+      }
+    // the operator fragments arrive before the column prefetch is issued:
+    // were they queued behind it, the loop's waits (taken over the entry path
+    // as well) would drain the whole prefetch on every unit
+    __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8));  // vmcnt(0)
+    __builtin_amdgcn_sched_barrier(0);
+  }
   const int Ln = L * n;
   auto base_of = [&](int c) -> int { return (c % L) + (c / L) * Ln; };
   const __amdgpu_buffer_rsrc_t xr = buf_rsrc(X, (size_t)ncols * n * sizeof(float));
@@ -346,7 +360,14 @@ __global__ __launch_bounds__(kStridedWaves * 64) void fd_strided_bf16_kernel(
       for (int t = 0; t < NM; ++t) {
         acc[t] = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kb = 0; kb < NK; ++kb) acc[t] = mfma3(wh[t][kb], wl[t][kb], xh[kb], xl[kb], acc[t]);
+        for (int kb = 0; kb < NK; ++kb) {
+          if constexpr (WL) {
+            const int o = (16 * t + cl) * LDV + 32 * kb + 8 * g;
+            acc[t] = mfma3(ld8(w1h + o), ld8(w1l + o), xh[kb], xl[kb], acc[t]);
+          } else {
+            acc[t] = mfma3(wh[t][kb], wl[t][kb], xh[kb], xl[kb], acc[t]);
+          }
+        }
       }
       if constexpr (FUSED) {
 #pragma unroll
@@ -425,23 +446,37 @@ int launch_slab(stls_ctx* h, const TI* X, TO* Z, bool fwd, const double* dotv, d
   return STLS_OK;
 }
 
+// forward operator in LDS (WL): measured on the d = 3, p = 4, 48-element
+// workload, the fused time pass runs in 23 us with it (128 registers, two
+// workgroups per CU) against 26 us without; the mode-3 pass is faster with
+// the operator in registers (17.5 us against 18.6 us)
+constexpr bool kSpaceOpsInLds = false;
+constexpr bool kTimeOpsInLds = true;
+
 template <int NM, bool FUSED>
 int launch_strided(stls_ctx* h, const float* X, float* Y, int L, int k, bool fwd, const double* lam_t) {
+  constexpr bool WL = FUSED ? kTimeOpsInLds : kSpaceOpsInLds;
   const DevDir& D = h->dd[k];
   const int n = D.n;
   const int ncols = (int)(h->ndof / n);
   const int nunits = (ncols + 15) / 16;
-  const int blocks = std::max(1, std::min((nunits + kStridedWaves - 1) / kStridedWaves, 256));
+  const int blocks = std::max(1, std::min((nunits + kStridedWaves - 1) / kStridedWaves, WL ? 512 : 256));
   constexpr int NK = (NM + 1) / 2;
-  const size_t shmem = FUSED ? sizeof(double) * 16 * NM + sizeof(__bf16) * 2 * 16 * NM * (NK * 32 + 8) +
-                                  sizeof(float) * kStridedWaves * 16 * (NK * 32 + 4)
-                             : 0;
+  const size_t op_bytes = sizeof(__bf16) * 2 * 16 * NM * (NK * 32 + 8);
+  const size_t shmem = (FUSED ? sizeof(double) * 16 * NM + op_bytes + sizeof(float) * kStridedWaves * 16 * (NK * 32 + 4)
+                              : 0) +
+                       (WL ? op_bytes : 0);
   const __bf16* Wh = (const __bf16*)(fwd ? D.Hfwd : D.Hbwd);
   const __bf16* Wl = (const __bf16*)(fwd ? D.Lfwd : D.Lbwd);
   const __bf16* W2h = FUSED ? (const __bf16*)D.Hbwd : nullptr;
   const __bf16* W2l = FUSED ? (const __bf16*)D.Lbwd : nullptr;
+  if (shmem > 65536) {
+    const hipError_t ea = hipFuncSetAttribute((const void*)fd_strided_bf16_kernel<NM, FUSED, WL>,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (ea != hipSuccess) return hip_fail(ea, "hipFuncSetAttribute(LDS)");
+  }
   prof_begin(h);
-  hipLaunchKernelGGL((fd_strided_bf16_kernel<NM, FUSED>), dim3(blocks), dim3(kStridedWaves * 64), shmem, h->stream, X,
+  hipLaunchKernelGGL((fd_strided_bf16_kernel<NM, FUSED, WL>), dim3(blocks), dim3(kStridedWaves * 64), shmem, h->stream, X,
                      Y, L, n, ncols, Wh, Wl, W2h, W2l, lam_t, h->lam_s, h->gate);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "fd_strided_bf16_kernel launch");
