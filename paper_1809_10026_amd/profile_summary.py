@@ -19,6 +19,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -51,13 +52,24 @@ def source_hash() -> str:
 FUSED_ARG = {"fd_strided_bf16_kernel": 1, "fd_mode_bf16x3_kernel": 4, "fd_mode_kernel": 6}
 
 
+def _mangled_template_args(name: str, frag: str):
+    """Template arguments of an Itanium-mangled name that the profiler left
+    mangled: integer (``Li4E``) and boolean (``Lb1E``) literals after ``frag``."""
+    rest = name.split(frag + "I", 1)[1] if frag + "I" in name else ""
+    return ["true" if v == "b1" else "false" if v == "b0" else v[1:]
+            for v in re.findall(r"L(i\d+|b[01])E", rest.split("EEv", 1)[0])]
+
+
 def kernel_class(name: str):
     for frag, cls in CLASSES:
         if frag in name:
             if cls is not None:
                 return cls
-            targs = name.split(frag + "<", 1)[1].split(">", 1)[0].split(",") if frag + "<" in name else []
-            fused = len(targs) > FUSED_ARG[frag] and targs[FUSED_ARG[frag]].strip() == "true"
+            if frag + "<" in name:
+                targs = [a.strip() for a in name.split(frag + "<", 1)[1].split(">", 1)[0].split(",")]
+            else:
+                targs = _mangled_template_args(name, frag)
+            fused = len(targs) > FUSED_ARG[frag] and targs[FUSED_ARG[frag]] == "true"
             return "fd_time" if fused else "fd_space"
     return None
 
