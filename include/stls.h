@@ -256,10 +256,22 @@ int stls_batch_prec_apply(stls_batch_handle b, const double* r, double* s);
 /* Batched PCG from x = 0 to ||r_i||/||b_i|| <= rtol for every problem i.
  * b, x: device, concatenated.  iters, relres: host arrays of nprob (may be
  * NULL).  Synchronises once per iteration (all problems' scalars in one copy).
+ * The kernels of one iteration (the same for every iteration: converged
+ * problems are masked on the device) are captured once per call into a
+ * hipGraph on the handle's stream and replayed; a stream that cannot be
+ * captured (the legacy default stream) gets direct launches.
  * Returns STLS_OK when all converged, STLS_ENOCONV if any hit maxit,
  * STLS_ENAN / STLS_EBREAKDOWN if any problem failed. */
 int stls_batch_pcg_solve(stls_batch_handle b, const double* bvec, double* x, double rtol, int maxit, int* iters,
                          double* relres);
+
+/* Replay the batched PCG iterations from a captured graph (on != 0, the
+ * default) or launch every kernel directly (on = 0); both run the same
+ * kernels in the same order and give identical results. */
+int stls_batch_set_graph(stls_batch_handle b, int on);
+/* 1 if the last stls_batch_pcg_solve replayed a captured graph, 0 if it
+ * launched the kernels directly, STLS_EINVAL for a NULL handle. */
+int stls_batch_graph_used(stls_batch_handle b);
 
 /* Per-kernel timing with HIP events on the handle's stream (0 = off). */
 int stls_set_profiling(stls_handle h, int on);

@@ -81,6 +81,8 @@ _sig = {
     "stls_batch_prec_apply": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
     "stls_batch_pcg_solve": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, ctypes.c_double, ctypes.c_int,
                                             _c_int_p, ctypes.POINTER(ctypes.c_double)]),
+    "stls_batch_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "stls_batch_graph_used": (ctypes.c_int, [ctypes.c_void_p]),
     "stls_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "stls_last_error": (ctypes.c_char_p, []),
 }
@@ -346,6 +348,17 @@ class Batch:
         _check(_lib.stls_batch_pcg_solve(self._h, _dev_ptr(b, self.total, "b"), _dev_ptr(x, self.total, "x"),
                                          float(rtol), int(maxit), its, rel), "stls_batch_pcg_solve", ok)
         return x, list(its), list(rel)
+
+    def set_graph(self, on):
+        """Replay the PCG iterations from a captured hipGraph (default) or launch directly."""
+        _check(_lib.stls_batch_set_graph(self._h, 1 if on else 0), "stls_batch_set_graph")
+
+    @property
+    def graph_used(self):
+        """Whether the last solve replayed a captured graph."""
+        v = _lib.stls_batch_graph_used(self._h)
+        _check(min(v, 0), "stls_batch_graph_used")
+        return bool(v)
 
 
 # ---------------------------------------------------------------------------

@@ -365,7 +365,7 @@ enum BFin { BF_BNORM = 0, BF_RHO0, BF_ALPHA, BF_RR, BF_BETA };
 // [beg[prob], end[prob]) and update of its scalars.
 __global__ __launch_bounds__(kT) void bfinalize_kernel(const double* __restrict__ partials, const int* __restrict__ beg,
                                                        const int* __restrict__ end, PcgScalars* __restrict__ S,
-                                                       int kind, int iter, double rtol) {
+                                                       int kind, double rtol) {
   __shared__ double red[4];
   const int prob = blockIdx.x;
   PcgScalars& s = S[prob];
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(kT) void bfinalize_kernel(const double* __restrict_
     case BF_RR: {
       const double rel = sqrt(t / s.bnorm2);
       s.relres = rel;
-      s.iters = iter;
+      s.iters += 1;  // active problems finalise r.r once per iteration (replayable as a graph)
       if (!isfinite(rel)) s.flag = 2; else if (rel <= s.rtol) s.done = 1;
       break;
     }
@@ -453,6 +453,12 @@ struct stls_batch_ctx {
   PcgScalars* S = nullptr;
   PcgScalars* Sh = nullptr;
   std::vector<int> last_iters;
+  bool use_graph = true;  // PCG iterations replayed from a captured hipGraph
+  // the solve runs on a stream of its own (capturable whatever the caller's
+  // stream is), ordered after and before the caller's stream by events
+  hipStream_t solve_stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  int graph_used = 0;  // 1 if the last solve replayed a captured graph
 };
 
 namespace {
@@ -495,6 +501,9 @@ void free_batch(stls_batch_ctx* B) {
   if (B->S) (void)hipFree(B->S);
   if (B->Sh) (void)hipHostFree(B->Sh);
   if (B->desc) (void)hipFree(B->desc);
+  if (B->ev_in) (void)hipEventDestroy(B->ev_in);
+  if (B->ev_out) (void)hipEventDestroy(B->ev_out);
+  if (B->solve_stream) (void)hipStreamDestroy(B->solve_stream);
   for (auto h : B->probs)
     if (h) stls_destroy(h);
   delete B;
@@ -502,9 +511,9 @@ void free_batch(stls_batch_ctx* B) {
 
 int grid_items(int n) { return std::max(1, std::min(n, 256 * 8)); }
 
-int bfin(stls_batch_ctx* B, const ItemList& L, int kind, int iter, double rtol) {
+int bfin(stls_batch_ctx* B, const ItemList& L, int kind, double rtol) {
   hipLaunchKernelGGL(bfinalize_kernel, dim3(B->nprob), dim3(kT), 0, B->stream, B->partials, L.beg, L.end, B->S, kind,
-                     iter, rtol);
+                     rtol);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? STLS_OK : hip_fail(e, "bfinalize_kernel launch");
 }
@@ -730,6 +739,12 @@ int stls_batch_setup(int nprob, int d, const int* nknots, const double* const* k
   }
   if (!st && hipMemsetAsync(B->S, 0, sizeof(PcgScalars) * nprob, B->stream) != hipSuccess) st = STLS_EHIP;
   if (!st && hipStreamSynchronize(B->stream) != hipSuccess) st = STLS_EHIP;
+  if (!st && (hipStreamCreateWithFlags(&B->solve_stream, hipStreamNonBlocking) != hipSuccess ||
+              hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming) != hipSuccess)) {
+    set_error("batch solve stream");
+    st = STLS_EHIP;
+  }
   if (st) {
     free_batch(B);
     return st;
@@ -770,42 +785,83 @@ int stls_batch_prec_apply(stls_batch_handle B, const double* r, double* s) {
   return bprec(B, r, s, nullptr);
 }
 
-int stls_batch_pcg_solve(stls_batch_handle B, const double* b, double* x, double rtol, int maxit, int* iters,
-                         double* relres) {
-  if (!B || !b || !x || b == x || !(rtol > 0.0) || maxit < 1) { set_error("bad batch arguments"); return STLS_EINVAL; }
+int stls_batch_graph_used(stls_batch_handle B) {
+  if (!B) { set_error("NULL batch handle"); return STLS_EINVAL; }
+  return B->graph_used;
+}
+
+int stls_batch_set_graph(stls_batch_handle B, int on) {
+  if (!B) { set_error("NULL batch handle"); return STLS_EINVAL; }
+  B->use_graph = on != 0;
+  return STLS_OK;
+}
+
+static int batch_pcg(stls_batch_handle B, const double* b, double* x, double rtol, int maxit, int* iters,
+                     double* relres) {
   hipStream_t st = B->stream;
   double* r = B->buf[0];
   double* z = B->buf[1];
   double* p = B->buf[2];
   double* q = B->buf[3];
-  int s;
+  int s = STLS_OK;
   const int gv = grid_items(B->vec.count);
   hipLaunchKernelGGL(bvec_kernel, dim3(gv), dim3(kT), 0, st, (int)BV_INIT, x, r, p, q, b, B->desc, B->vec.dev,
                      B->vec.count, B->S, B->partials);
-  if ((s = bfin(B, B->vec, BF_BNORM, 0, rtol))) return s;
+  if ((s = bfin(B, B->vec, BF_BNORM, rtol))) return s;
   if ((s = bprec(B, r, z, r))) return s;
-  if ((s = bfin(B, B->fd[0], BF_RHO0, 0, rtol))) return s;
+  if ((s = bfin(B, B->fd[0], BF_RHO0, rtol))) return s;
   hipLaunchKernelGGL(bcopy_kernel, dim3(gv), dim3(kT), 0, st, p, z, B->desc, B->vec.dev, B->vec.count, B->S);
-  int status = STLS_ENOCONV;
-  for (int k = 1; k <= maxit; ++k) {
-    if ((s = bmatvec(B, p, q, p))) return s;
-    if ((s = bfin(B, B->outer_all, BF_ALPHA, k, rtol))) return s;
+  // One PCG iteration of every problem; converged or broken-down problems
+  // are masked by every kernel (their scalars say so), so the body is the
+  // same in every iteration and can be replayed from a graph.
+  auto body = [&]() -> int {
+    int t;
+    if ((t = bmatvec(B, p, q, p))) return t;
+    if ((t = bfin(B, B->outer_all, BF_ALPHA, rtol))) return t;
     hipLaunchKernelGGL(bvec_kernel, dim3(gv), dim3(kT), 0, st, (int)BV_XR, x, r, p, q, b, B->desc, B->vec.dev,
                        B->vec.count, B->S, B->partials);
-    if ((s = bfin(B, B->vec, BF_RR, k, rtol))) return s;
-    if ((s = read_scalars(B))) return s;
+    if ((t = bfin(B, B->vec, BF_RR, rtol))) return t;
+    if ((t = bprec(B, r, z, r))) return t;
+    if ((t = bfin(B, B->fd[0], BF_BETA, rtol))) return t;
+    hipLaunchKernelGGL(bvec_kernel, dim3(gv), dim3(kT), 0, st, (int)BV_P, x, r, p, z, b, B->desc, B->vec.dev,
+                       B->vec.count, B->S, B->partials);
+    const hipError_t le = hipGetLastError();
+    return le == hipSuccess ? STLS_OK : hip_fail(le, "batched PCG launch");
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (B->use_graph) {  // capture failure falls back to direct launches
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      const int cs = body();
+      if (hipStreamEndCapture(st, &graph) != hipSuccess || cs != STLS_OK ||
+          hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        graph = nullptr;
+        exec = nullptr;
+        (void)hipGetLastError();
+      }
+    }
+  }
+  B->graph_used = exec != nullptr;
+  int status = STLS_ENOCONV;
+  for (int k = 1; k <= maxit; ++k) {
+    if (exec) {
+      const hipError_t ge = hipGraphLaunch(exec, st);
+      if (ge != hipSuccess) { s = hip_fail(ge, "hipGraphLaunch"); break; }
+    } else if ((s = body())) {
+      break;
+    }
+    if ((s = read_scalars(B))) break;
     bool all = true, bad = false;
     for (int i = 0; i < B->nprob; ++i) {
       if (B->Sh[i].flag) bad = true;
       else if (!B->Sh[i].done) all = false;
     }
     if (all) { status = bad ? STLS_EBREAKDOWN : STLS_OK; break; }
-    if (k == maxit) break;
-    if ((s = bprec(B, r, z, r))) return s;
-    if ((s = bfin(B, B->fd[0], BF_BETA, k, rtol))) return s;
-    hipLaunchKernelGGL(bvec_kernel, dim3(gv), dim3(kT), 0, st, (int)BV_P, x, r, p, z, b, B->desc, B->vec.dev,
-                       B->vec.count, B->S, B->partials);
   }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (s) return s;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "batched PCG launch");
   if ((s = read_scalars(B))) return s;
@@ -819,6 +875,26 @@ int stls_batch_pcg_solve(stls_batch_handle B, const double* b, double* x, double
   if (nan) { set_error("non-finite value in a batched problem"); return STLS_ENAN; }
   if (status == STLS_ENOCONV) set_error("some batched problems did not reach rtol within maxit");
   return status;
+}
+
+int stls_batch_pcg_solve(stls_batch_handle B, const double* b, double* x, double rtol, int maxit, int* iters,
+                         double* relres) {
+  if (!B || !b || !x || b == x || !(rtol > 0.0) || maxit < 1) { set_error("bad batch arguments"); return STLS_EINVAL; }
+  // run on the batch's own stream, after the caller's stream's earlier work
+  // and before its later work
+  hipStream_t caller = B->stream;
+  if (hipEventRecord(B->ev_in, caller) != hipSuccess || hipStreamWaitEvent(B->solve_stream, B->ev_in, 0) != hipSuccess) {
+    set_error("batch solve stream ordering");
+    return STLS_EHIP;
+  }
+  B->stream = B->solve_stream;
+  const int st = batch_pcg(B, b, x, rtol, maxit, iters, relres);
+  B->stream = caller;
+  if (hipEventRecord(B->ev_out, B->solve_stream) != hipSuccess || hipStreamWaitEvent(caller, B->ev_out, 0) != hipSuccess) {
+    set_error("batch solve stream ordering");
+    return STLS_EHIP;
+  }
+  return st;
 }
 
 }  // extern "C"

@@ -102,3 +102,42 @@ def test_full_uneven_batch_converges():
         xs, it_s, _ = S.solve(bt[off[i]:off[i + 1]].contiguous(), rtol=1e-8)
         assert abs(its[i] - it_s) <= 1
         assert rel_err(to_host(x[off[i]:off[i + 1]]), to_host(xs)) < 1e-6
+
+
+@pytest.mark.parametrize("full", [False, True])
+def test_graph_replay_matches_direct_launches(full):
+    """The batched solve replays one captured iteration as a hipGraph.  It
+    must give exactly (bitwise) what direct launches of the same kernels
+    give, on repeated solves with eager batch work between them."""
+    import time
+
+    import torch
+    if full:
+        nel, p, kappa = batch_params()
+        probs = [(*batch_problem_knots(nel[i], p[i]), float(kappa[i])) for i in range(len(p))]
+        B = stls.Batch(probs)
+    else:
+        B, probs = _batch(SMALL)
+    b = to_dev(uniform_pm1(B.total, 63))
+    B.set_graph(False)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    x0, its0, rel0 = B.solve(b, rtol=1e-8, maxit=500)
+    torch.cuda.synchronize()
+    t_direct = time.perf_counter() - t
+    assert not B.graph_used
+    x0 = to_host(x0)
+    B.set_graph(True)
+    for rep in range(2):
+        y = B.matvec(b)  # eager work between the graph solves
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x1, its1, rel1 = B.solve(b, rtol=1e-8, maxit=500)
+        torch.cuda.synchronize()
+        t_graph = time.perf_counter() - t
+        assert B.graph_used  # the captured iteration was replayed
+        assert its1 == its0 and rel1 == rel0
+        assert np.array_equal(to_host(x1), x0)
+        assert np.isfinite(to_host(y)).all()
+    print(f"{len(probs)} problems, {max(its0)} iterations: direct {t_direct * 1e3:.1f} ms, graph {t_graph * 1e3:.1f} ms",
+          flush=True)
