@@ -197,6 +197,7 @@ def main():
                     avg_us=round(dom["avg_us"], 3))
 
     err_norms = gpu_error_norms(stls, torch)
+    batch = gpu_batch(stls, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -230,6 +231,7 @@ def main():
         "matvec_dof_per_s": N / mv_s,
         "diag_scaled_prec": scaled,
         "error_norms": err_norms,
+        "batch": batch,
         "setup_s": setup_s,
         "roofline": roofline,
         "roofline_note": "kernel durations from HIP events recorded around every launch on the solver's "
@@ -271,6 +273,37 @@ def gpu_error_norms(stls, torch, reps=3):
                         "exact u = sin(pi x) sin(pi y) sin(pi t), p+3 Gauss points per span",
             "seconds": dt, "grid_points": grid, "fields": 2 * c["d"] + 2, "grid_points_per_s": grid / dt,
             "norms": res}
+
+
+def gpu_batch(stls, torch, steps=3):
+    """Batched PCG (256 uneven d = 2 problems: n_el per direction uniform on
+    16..96, p uniform on {2..5}, kappa log-uniform on [0.1, 10], right-hand
+    sides U[-1, 1] with seeds 20180927 + i), rtol 1e-8, FP64 FD."""
+    import numpy as np
+
+    from stls_inputs import batch_params, batch_problem_knots, uniform_pm1
+    nel, p, kappa = batch_params()
+    probs = [(*batch_problem_knots(nel[i], p[i]), float(kappa[i])) for i in range(len(p))]
+    t = time.perf_counter()
+    B = stls.Batch(probs)
+    setup_s = time.perf_counter() - t
+    off = B.offsets
+    b = torch.as_tensor(np.concatenate([uniform_pm1(off[i + 1] - off[i], 20180927 + i)
+                                        for i in range(len(probs))])).cuda()
+    x = torch.empty_like(b)
+    B.solve(b, 1e-8, 500, out=x)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        _, its, rels = B.solve(b, 1e-8, 500, out=x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    log(f"batch: {dt*1e3:.1f} ms for {B.total} unknowns, {max(its)} iterations")
+    return {"workload": "256 independent d=2 problems, n_el per direction U{16..96}, p U{2..5}, "
+                        "kappa 10^U(-1,1), RHS U[-1,1] (seeds 20180927+i), rtol 1e-8, FP64 FD",
+            "total_dof": int(B.total), "seconds": dt, "dof_per_s": B.total / dt, "max_iters": int(max(its)),
+            "iteration_ms": dt / max(its) * 1e3, "graph_replay": bool(B.graph_used), "setup_s": setup_s,
+            "max_relres": float(max(rels))}
 
 
 def cpu_error_norms(nel=32):

@@ -165,32 +165,42 @@ __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, d
 }
 
 // Inner stage of the matvec for d = 2: A = M1 x, B = J1 x, C = K1 x along the
-// contiguous columns of n1 entries (chunks of kInChunk elements).
+// contiguous columns of n1 entries (chunks of kInChunk elements), for the
+// problems of degree PP: the 2PP+1 taps are unrolled with clamped columns
+// (band entries outside the matrix are stored as zeros, so the clamped
+// reads add nothing).
+template <int PP>
 __global__ __launch_bounds__(kT) void binner1_kernel(const double* __restrict__ x, double* __restrict__ A,
                                                      double* __restrict__ Bo, double* __restrict__ C,
                                                      const BProb* __restrict__ P, const Item* __restrict__ items,
                                                      int nitems, const PcgScalars* __restrict__ S) {
+  constexpr int BW = 2 * PP + 1;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item I = items[it];
     if (skip(S, I.prob)) continue;
     const BProb& B = P[I.prob];
-    const int n1 = B.n[0], p = B.p[0], bw = 2 * p + 1;
+    const int n1 = B.n[0];
+    const double* __restrict__ Mb = B.M[0];
+    const double* __restrict__ Jb = B.J[0];
+    const double* __restrict__ Kb = B.K[0];
+    const long long off = B.off;
     const int e0 = I.idx * kInChunk, e1 = min(B.N, e0 + kInChunk);
-    const double* xp = x + B.off;
+    const double* xp = x + off;
     for (int e = e0 + threadIdx.x; e < e1; e += kT) {
       const int i = e % n1, col0 = e - i;
+      double v[BW];
+#pragma unroll
+      for (int o = 0; o < BW; ++o) v[o] = xp[col0 + min(max(i + o - PP, 0), n1 - 1)];
       double a = 0.0, b = 0.0, c = 0.0;
-      for (int o = 0; o < bw; ++o) {
-        const int j = i + o - p;
-        if (j < 0 || j >= n1) continue;
-        const double v = xp[col0 + j];
-        a += B.M[0][i * bw + o] * v;
-        b += B.J[0][i * bw + o] * v;
-        c += B.K[0][i * bw + o] * v;
+#pragma unroll
+      for (int o = 0; o < BW; ++o) {
+        a += Mb[i * BW + o] * v[o];
+        b += Jb[i * BW + o] * v[o];
+        c += Kb[i * BW + o] * v[o];
       }
-      A[B.off + e] = a;
-      Bo[B.off + e] = b;
-      C[B.off + e] = c;
+      A[off + e] = a;
+      Bo[off + e] = b;
+      C[off + e] = c;
     }
   }
 }
@@ -442,7 +452,9 @@ struct stls_batch_ctx {
   std::vector<int64_t> off;  // nprob + 1
   int64_t total = 0;
   ItemList fd[4];       // FD passes per direction (index d = fused time)
-  ItemList vec, inner;
+  ItemList vec;
+  std::vector<ItemList> inner;   // d = 2 inner-stage items per degree group
+  std::vector<int> inner_p;      // degree of each group
   std::vector<ItemList> outer;   // per degree group
   std::vector<int> outer_p;      // degree of each group
   ItemList outer_all;            // concatenation (for the dot ranges)
@@ -492,7 +504,7 @@ void free_batch(stls_batch_ctx* B) {
   if (!B) return;
   for (auto& L : B->fd) free_list(L);
   free_list(B->vec);
-  free_list(B->inner);
+  for (auto& L : B->inner) free_list(L);
   for (auto& L : B->outer) free_list(L);
   free_list(B->outer_all);
   for (double* p : B->buf)
@@ -568,8 +580,23 @@ int bmatvec(stls_batch_ctx* B, const double* x, double* y, const double* dotv) {
   const double* Bv = nullptr;
   const double* C = nullptr;
   if (B->d == 2) {
-    hipLaunchKernelGGL(binner1_kernel, dim3(grid_items(B->inner.count)), dim3(kT), 0, st, x, B->buf[6], B->buf[7],
-                       B->buf[8], B->desc, B->inner.dev, B->inner.count, B->S);
+    for (size_t g = 0; g < B->inner.size(); ++g) {
+      const ItemList& L = B->inner[g];
+      if (L.count == 0) continue;
+      void (*kern)(const double*, double*, double*, double*, const BProb*, const Item*, int, const PcgScalars*) =
+          nullptr;
+      switch (B->inner_p[g]) {
+        case 1: kern = binner1_kernel<1>; break;
+        case 2: kern = binner1_kernel<2>; break;
+        case 3: kern = binner1_kernel<3>; break;
+        case 4: kern = binner1_kernel<4>; break;
+        case 5: kern = binner1_kernel<5>; break;
+        case 6: kern = binner1_kernel<6>; break;
+        default: set_error("batch degree not supported"); return STLS_EINVAL;
+      }
+      hipLaunchKernelGGL(kern, dim3(grid_items(L.count)), dim3(kT), 0, st, x, B->buf[6], B->buf[7], B->buf[8],
+                         B->desc, L.dev, L.count, B->S);
+    }
     A = B->buf[6];
     Bv = B->buf[7];
     C = B->buf[8];
@@ -698,7 +725,21 @@ int stls_batch_setup(int nprob, int d, const int* nknots, const double* const* k
   int st = upload_vec(&B->desc, B->hdesc, B->stream);
   for (int k = 0; k <= d && !st; ++k) st = make_list(B, B->fd[k], cnt_fd[k]);
   if (!st) st = make_list(B, B->vec, cnt_vec);
-  if (!st && d == 2) st = make_list(B, B->inner, cnt_in);
+  if (!st && d == 2) {  // inner items grouped by degree
+    std::vector<int> uniq;
+    for (int i = 0; i < nprob; ++i) uniq.push_back(B->hdesc[i].p[0]);
+    std::sort(uniq.begin(), uniq.end());
+    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    for (int p : uniq) {
+      std::vector<int> members;
+      for (int i = 0; i < nprob; ++i)
+        if (B->hdesc[i].p[0] == p) members.push_back(i);
+      ItemList L;
+      if ((st = make_list(B, L, cnt_in, &members))) break;
+      B->inner.push_back(L);
+      B->inner_p.push_back(p);
+    }
+  }
   // outer items grouped by degree; the concatenated list fixes the partial ranges
   if (!st) {
     std::vector<int> degs;
