@@ -116,3 +116,34 @@ def test_fullsize_pcg(full):
     ref = sols[(0, False)]
     for key, xo in sols.items():
         assert rel_err(xo, ref) < 2 * 3 * 10 * CFG["rtol"], key
+
+
+@pytest.mark.parametrize("rhs", ["manufactured", "random"])
+def test_fullsize_d2_workload_against_oracle(rhs):
+    """The 2-D workload at full size (p = 3, 64 elements per direction,
+    N = 278,850): manufactured sin(pi x) sin(pi y) sin(pi t) and the
+    U[-1, 1] right-hand side (seed 1809), FP64 FD.  The oracle's own FD-PCG
+    runs at this size in seconds: iteration counts within one, solutions to
+    the solve tolerance times the preconditioned condition bound (2d), true
+    residual by the oracle's matvec."""
+    from oracle import assemble, pcg as opcg
+    c = CONFIGS["d2_p3_nel64"]
+    knots, degs = problem_knots(c["d"], c["n_el"], c["p"])
+    P = osys.Problem(knots, degs)
+    if rhs == "manufactured":
+        pi = np.pi
+        s = lambda x: np.sin(pi * x)
+        F = osys.vec(assemble.load_separable(knots, degs, [(pi, [s, s], lambda t: np.cos(pi * t)),
+                                                           (2 * pi * pi, [s, s], lambda t: np.sin(pi * t))]))
+    else:
+        F = uniform_pm1(P.ndof, c["seed"])
+    S = stls.Solver(knots, degs)
+    assert S.ndof == 278850
+    x, it, rel = S.solve(to_dev(F), rtol=c["rtol"], maxit=200)
+    xo = to_host(x)
+    fdo = ofd.FD(P)
+    x_ref, info = opcg.pcg(lambda v: osys.vec(P.matvec(v)), lambda v: osys.vec(fdo.apply(v)), F, c["rtol"])
+    true_rel = np.linalg.norm(F - osys.vec(P.matvec(xo))) / np.linalg.norm(F)
+    print(f"d2 {rhs}: {it} iterations (oracle {info['iters']}), true relres {true_rel:.2e}", flush=True)
+    assert abs(it - info["iters"]) <= 1 and rel <= c["rtol"] and true_rel < 2 * c["rtol"]
+    assert rel_err(xo, x_ref) < 2 * 2 * 10 * c["rtol"]
