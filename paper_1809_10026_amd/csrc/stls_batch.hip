@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <array>
 #include <thread>
 #include <vector>
 
@@ -75,12 +76,17 @@ __device__ inline bool skip(const PcgScalars* S, int prob) { return S[prob].done
 // zero padded to npad) read from global memory as W[j*npad + i].  mode: space
 // direction (0..d-1) or d = fused time (forward product, FP64 division by
 // lambda_t[i] + lambda_s[c], backward product).  TRANS: contiguous mode 0.
-template <bool TRANS, bool FUSED, bool DOT>
+// NMT: 16-row tiles of the operator (the items of one launch are those of
+// the problems whose direction has that padded size); the panel is staged in
+// NMT * 16 rows of dynamic LDS.  item0: index of items[0] in the pass's
+// list (partial sums are indexed by list position).
+template <bool TRANS, bool FUSED, bool DOT, int NMT>
 __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, double* __restrict__ Y,
                                                  const BProb* __restrict__ P, const Item* __restrict__ items,
-                                                 int nitems, int mode, int bwd, const PcgScalars* __restrict__ S,
-                                                 const double* __restrict__ dotv, double* __restrict__ partials) {
-  __shared__ double Xs[kBNM * 16 * kBLdx];
+                                                 int nitems, int item0, int mode, int bwd,
+                                                 const PcgScalars* __restrict__ S, const double* __restrict__ dotv,
+                                                 double* __restrict__ partials) {
+  extern __shared__ __align__(16) double Xs[];  // NMT * 16 x kBLdx
   __shared__ double red[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ccol = wave * 16 + (lane & 15), krow = lane >> 4;
@@ -108,14 +114,14 @@ __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, d
       Xs[j * kBLdx + c] = ok ? v : 0.0;
     }
     __syncthreads();
-    d4b_t acc[kBNM];
+    d4b_t acc[NMT];
     auto gemm = [&](const double* Wm) {
 #pragma unroll
-      for (int t = 0; t < kBNM; ++t) acc[t] = d4b_t{0, 0, 0, 0};
+      for (int t = 0; t < NMT; ++t) acc[t] = d4b_t{0, 0, 0, 0};
       for (int k0 = 0; k0 < n; k0 += 4) {
         const double xv = Xs[(k0 + krow) * kBLdx + ccol];
 #pragma unroll
-        for (int t = 0; t < kBNM; ++t) {
+        for (int t = 0; t < NMT; ++t) {
           if (t < nm) {
             const double wv = Wm[(size_t)(k0 + krow) * npad + t * 16 + (lane & 15)];
             if (TRANS) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, wv, acc[t], 0, 0, 0);
@@ -130,7 +136,7 @@ __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, d
       const double ls = B.lam_s[min(cc, ncols - 1)];
       __syncthreads();
 #pragma unroll
-      for (int t = 0; t < kBNM; ++t)
+      for (int t = 0; t < NMT; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = t * 16 + (lane >> 4) + 4 * r;
@@ -144,7 +150,7 @@ __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, d
     }
     double ds = 0.0;
 #pragma unroll
-    for (int t = 0; t < kBNM; ++t)
+    for (int t = 0; t < NMT; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         if (t >= nm) continue;
@@ -159,7 +165,7 @@ __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, d
       }
     if (DOT) {
       const double s = bsum(ds, red);
-      if (tid == 0) partials[it] = s;
+      if (tid == 0) partials[item0 + it] = s;
     }
   }
 }
@@ -451,7 +457,8 @@ struct stls_batch_ctx {
   BProb* desc = nullptr;
   std::vector<int64_t> off;  // nprob + 1
   int64_t total = 0;
-  ItemList fd[4];       // FD passes per direction (index d = fused time)
+  ItemList fd[4];       // FD passes per direction (index d = fused time), items ordered by padded size
+  std::vector<std::array<int, 3>> fd_grp[4];  // per pass: {16-row tiles, first item, item count}
   ItemList vec;
   std::vector<ItemList> inner;   // d = 2 inner-stage items per degree group
   std::vector<int> inner_p;      // degree of each group
@@ -530,48 +537,60 @@ int bfin(stls_batch_ctx* B, const ItemList& L, int kind, double rtol) {
   return e == hipSuccess ? STLS_OK : hip_fail(e, "bfinalize_kernel launch");
 }
 
+// One FD pass over all problems: a launch per padded-size group.
+template <bool TRANS, bool FUSED, bool DOT>
+int bfd_pass(stls_batch_ctx* B, int k, const double* in, double* out, int bwd, const double* dotv) {
+  for (const auto& g : B->fd_grp[k]) {
+    const int nm = g[0], first = g[1], count = g[2];
+    if (count == 0) continue;
+    void (*kern)(const double*, double*, const BProb*, const Item*, int, int, int, int, const PcgScalars*,
+                 const double*, double*) = nullptr;
+    switch (nm) {
+      case 1: kern = bfd_kernel<TRANS, FUSED, DOT, 1>; break;
+      case 2: kern = bfd_kernel<TRANS, FUSED, DOT, 2>; break;
+      case 3: kern = bfd_kernel<TRANS, FUSED, DOT, 3>; break;
+      case 4: kern = bfd_kernel<TRANS, FUSED, DOT, 4>; break;
+      case 5: kern = bfd_kernel<TRANS, FUSED, DOT, 5>; break;
+      case 6: kern = bfd_kernel<TRANS, FUSED, DOT, 6>; break;
+      case 7: kern = bfd_kernel<TRANS, FUSED, DOT, 7>; break;
+      default: set_error("batch: direction too large for the FD kernel"); return STLS_EINVAL;
+    }
+    const size_t shmem = sizeof(double) * (size_t)nm * 16 * kBLdx;
+    hipLaunchKernelGGL(kern, dim3(grid_items(count)), dim3(kT), shmem, B->stream, in, out, B->desc,
+                       B->fd[k].dev + first, count, first, k, bwd, B->S, dotv, B->partials);
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? STLS_OK : hip_fail(e, "batched FD launch");
+}
+
 int bprec(stls_batch_ctx* B, const double* r, double* s, const double* dotv) {
   const int d = B->d;
-  double* f0 = B->buf[4];
-  double* f1 = B->buf[5];
+  double* outs[2] = {B->buf[4], B->buf[5]};
   const double* in = r;
-  double* outs[2] = {f0, f1};
-  int cur = 0;
-  hipStream_t st = B->stream;
+  int cur = 0, st;
   // forward space modes
   for (int k = 0; k < d; ++k) {
     double* out = outs[cur];
-    if (k == 0)
-      hipLaunchKernelGGL((bfd_kernel<true, false, false>), dim3(grid_items(B->fd[k].count)), dim3(kT), 0, st, in, out,
-                         B->desc, B->fd[k].dev, B->fd[k].count, k, 0, B->S, nullptr, nullptr);
-    else
-      hipLaunchKernelGGL((bfd_kernel<false, false, false>), dim3(grid_items(B->fd[k].count)), dim3(kT), 0, st, in, out,
-                         B->desc, B->fd[k].dev, B->fd[k].count, k, 0, B->S, nullptr, nullptr);
+    st = k == 0 ? bfd_pass<true, false, false>(B, k, in, out, 0, nullptr)
+                : bfd_pass<false, false, false>(B, k, in, out, 0, nullptr);
+    if (st) return st;
     in = out;
     cur ^= 1;
   }
-  hipLaunchKernelGGL((bfd_kernel<false, true, false>), dim3(grid_items(B->fd[d].count)), dim3(kT), 0, st, in,
-                     outs[cur], B->desc, B->fd[d].dev, B->fd[d].count, d, 0, B->S, nullptr, nullptr);
+  if ((st = bfd_pass<false, true, false>(B, d, in, outs[cur], 0, nullptr))) return st;
   in = outs[cur];
   cur ^= 1;
   for (int k = d - 1; k >= 0; --k) {
     double* out = (k == 0) ? s : outs[cur];
-    if (k == 0) {
-      if (dotv)
-        hipLaunchKernelGGL((bfd_kernel<true, false, true>), dim3(grid_items(B->fd[k].count)), dim3(kT), 0, st, in, out,
-                           B->desc, B->fd[k].dev, B->fd[k].count, k, 1, B->S, dotv, B->partials);
-      else
-        hipLaunchKernelGGL((bfd_kernel<true, false, false>), dim3(grid_items(B->fd[k].count)), dim3(kT), 0, st, in,
-                           out, B->desc, B->fd[k].dev, B->fd[k].count, k, 1, B->S, nullptr, nullptr);
-    } else {
-      hipLaunchKernelGGL((bfd_kernel<false, false, false>), dim3(grid_items(B->fd[k].count)), dim3(kT), 0, st, in,
-                         out, B->desc, B->fd[k].dev, B->fd[k].count, k, 1, B->S, nullptr, nullptr);
-    }
+    if (k == 0)
+      st = dotv ? bfd_pass<true, false, true>(B, k, in, out, 1, dotv) : bfd_pass<true, false, false>(B, k, in, out, 1, nullptr);
+    else
+      st = bfd_pass<false, false, false>(B, k, in, out, 1, nullptr);
+    if (st) return st;
     in = out;
     cur ^= 1;
   }
-  hipError_t e = hipGetLastError();
-  return e == hipSuccess ? STLS_OK : hip_fail(e, "batched FD launch");
+  return STLS_OK;
 }
 
 int bmatvec(stls_batch_ctx* B, const double* x, double* y, const double* dotv) {
@@ -723,7 +742,23 @@ int stls_batch_setup(int nprob, int d, const int* nknots, const double* const* k
   }
   B->total = B->off[nprob];
   int st = upload_vec(&B->desc, B->hdesc, B->stream);
-  for (int k = 0; k <= d && !st; ++k) st = make_list(B, B->fd[k], cnt_fd[k]);
+  // FD items of each pass ordered by the direction's padded size, one group
+  // (kernel instance with that many tiles) per size
+  for (int k = 0; k <= d && !st; ++k) {
+    std::vector<int> order(nprob);
+    for (int i = 0; i < nprob; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return B->hdesc[a].npad[k] < B->hdesc[b].npad[k]; });
+    st = make_list(B, B->fd[k], cnt_fd[k], &order);
+    int first = 0;
+    for (size_t j = 0; j < order.size();) {
+      const int nm = B->hdesc[order[j]].npad[k] / 16;
+      int count = 0;
+      for (; j < order.size() && B->hdesc[order[j]].npad[k] / 16 == nm; ++j) count += cnt_fd[k][order[j]];
+      B->fd_grp[k].push_back({nm, first, count});
+      first += count;
+    }
+  }
   if (!st) st = make_list(B, B->vec, cnt_vec);
   if (!st && d == 2) {  // inner items grouped by degree
     std::vector<int> uniq;
