@@ -94,7 +94,8 @@ __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, d
     const Item I = items[it];
     const BProb& B = P[I.prob];
     if (skip(S, I.prob)) continue;
-    const int n = B.n[mode], npad = B.npad[mode], nm = npad / 16;
+    constexpr int npad = NMT * 16;  // == B.npad[mode] for every item of this launch
+    const int n = B.n[mode];
     int L = 1;
     for (int m = 0; m < mode; ++m) L *= B.n[m];
     const int ncols = B.N / n;
@@ -103,30 +104,62 @@ __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, d
     double* Yp = Y + B.off;
     const int c0 = I.idx * kBCols;
     auto base = [&](int cc) -> int { return TRANS ? cc * n : (cc % L) + (cc / L) * L * n; };
-    __syncthreads();
-    for (int e = tid; e < kBCols * npad; e += kT) {
+    // panel load: all 4 * NMT loads of a thread in flight before the LDS writes
+    constexpr int kLd = kBCols * npad / kT;
+    double v[kLd];
+#pragma unroll
+    for (int q = 0; q < kLd; ++q) {
+      const int e = tid + q * kT;
       int j, c;
       if (TRANS) { c = e / npad; j = e - c * npad; }
       else { j = e / kBCols; c = e - j * kBCols; }
       const int cc = c0 + c;
       const bool ok = cc < ncols && j < n;
-      const double v = Xp[ok ? (size_t)base(cc) + (size_t)j * L : 0];
-      Xs[j * kBLdx + c] = ok ? v : 0.0;
+      v[q] = Xp[ok ? (size_t)base(cc) + (size_t)j * L : 0];
+      v[q] = ok ? v[q] : 0.0;
+    }
+    __syncthreads();  // previous item's LDS reads are done
+#pragma unroll
+    for (int q = 0; q < kLd; ++q) {
+      const int e = tid + q * kT;
+      int j, c;
+      if (TRANS) { c = e / npad; j = e - c * npad; }
+      else { j = e / kBCols; c = e - j * kBCols; }
+      Xs[j * kBLdx + c] = v[q];
     }
     __syncthreads();
     d4b_t acc[NMT];
+    // Y tile rows t*16.., k in 16-row blocks; the W fragments of block kb + 1
+    // are loaded while block kb's MFMAs run (W is zero padded to npad rows)
     auto gemm = [&](const double* Wm) {
 #pragma unroll
       for (int t = 0; t < NMT; ++t) acc[t] = d4b_t{0, 0, 0, 0};
-      for (int k0 = 0; k0 < n; k0 += 4) {
-        const double xv = Xs[(k0 + krow) * kBLdx + ccol];
+      double wc[4][NMT], wn[4][NMT];
+      auto wload = [&](double (&w)[4][NMT], int kb) {
 #pragma unroll
-        for (int t = 0; t < NMT; ++t) {
-          if (t < nm) {
-            const double wv = Wm[(size_t)(k0 + krow) * npad + t * 16 + (lane & 15)];
-            if (TRANS) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, wv, acc[t], 0, 0, 0);
-            else acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(wv, xv, acc[t], 0, 0, 0);
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+          for (int t = 0; t < NMT; ++t)
+            w[s4][t] = Wm[(size_t)(kb * 16 + s4 * 4 + krow) * npad + t * 16 + (lane & 15)];
+      };
+      wload(wc, 0);
+#pragma unroll
+      for (int kb = 0; kb < NMT; ++kb) {
+        if (kb + 1 < NMT) wload(wn, kb + 1);
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const double xv = Xs[(kb * 16 + s4 * 4 + krow) * kBLdx + ccol];
+#pragma unroll
+          for (int t = 0; t < NMT; ++t) {
+            if (TRANS) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, wc[s4][t], acc[t], 0, 0, 0);
+            else acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(wc[s4][t], xv, acc[t], 0, 0, 0);
           }
+        }
+        if (kb + 1 < NMT) {
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int t = 0; t < NMT; ++t) wc[s4][t] = wn[s4][t];
         }
       }
     };
@@ -140,10 +173,8 @@ __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, d
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = t * 16 + (lane >> 4) + 4 * r;
-          if (t < nm) {
-            const double v = acc[t][r] / (B.lam_t[min(i, n - 1)] + ls);
-            Xs[i * kBLdx + ccol] = i < n ? v : 0.0;
-          }
+          const double q = acc[t][r] / (B.lam_t[min(i, n - 1)] + ls);
+          Xs[i * kBLdx + ccol] = i < n ? q : 0.0;
         }
       __syncthreads();
       gemm(B.Ab[mode]);
@@ -153,7 +184,6 @@ __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, d
     for (int t = 0; t < NMT; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        if (t >= nm) continue;
         int i, cc;
         if (TRANS) { cc = c0 + wave * 16 + (lane >> 4) + 4 * r; i = t * 16 + (lane & 15); }
         else { cc = c0 + ccol; i = t * 16 + (lane >> 4) + 4 * r; }
