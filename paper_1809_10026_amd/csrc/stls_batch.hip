@@ -89,7 +89,12 @@ __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, d
   extern __shared__ __align__(16) double Xs[];  // NMT * 16 x kBLdx
   __shared__ double red[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int ccol = wave * 16 + (lane & 15), krow = lane >> 4;
+  // 2 x 2 wave split of the output panel: wave (wr, wq) owns row tiles
+  // [wr * kH, wr * kH + kH) (the last one may be past NMT: computed on a
+  // clamped operand column, not stored) and columns [32 wq, 32 wq + 32)
+  constexpr int kH = (NMT + 1) / 2;
+  const int wr = wave >> 1, wq = wave & 1;
+  const int col0 = wq * 32 + (lane & 15), krow = lane >> 4;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item I = items[it];
     const BProb& B = P[I.prob];
@@ -128,19 +133,21 @@ __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, d
       Xs[j * kBLdx + c] = v[q];
     }
     __syncthreads();
-    d4b_t acc[NMT];
-    // Y tile rows t*16.., k in 16-row blocks; the W fragments of block kb + 1
-    // are loaded while block kb's MFMAs run (W is zero padded to npad rows)
+    d4b_t acc[kH][2];
+    auto tile = [&](int t) { return min(wr * kH + t, NMT - 1); };
+    // k in 16-row blocks; the W fragments of block kb + 1 are loaded while
+    // block kb's MFMAs run (W is zero padded to npad rows); each fragment
+    // feeds the wave's two column tiles
     auto gemm = [&](const double* Wm) {
 #pragma unroll
-      for (int t = 0; t < NMT; ++t) acc[t] = d4b_t{0, 0, 0, 0};
-      double wc[4][NMT], wn[4][NMT];
-      auto wload = [&](double (&w)[4][NMT], int kb) {
+      for (int t = 0; t < kH; ++t) acc[t][0] = acc[t][1] = d4b_t{0, 0, 0, 0};
+      double wc[4][kH], wn[4][kH];
+      auto wload = [&](double (&w)[4][kH], int kb) {
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-          for (int t = 0; t < NMT; ++t)
-            w[s4][t] = Wm[(size_t)(kb * 16 + s4 * 4 + krow) * npad + t * 16 + (lane & 15)];
+          for (int t = 0; t < kH; ++t)
+            w[s4][t] = Wm[(size_t)(kb * 16 + s4 * 4 + krow) * npad + tile(t) * 16 + (lane & 15)];
       };
       wload(wc, 0);
 #pragma unroll
@@ -148,51 +155,66 @@ __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, d
         if (kb + 1 < NMT) wload(wn, kb + 1);
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
-          const double xv = Xs[(kb * 16 + s4 * 4 + krow) * kBLdx + ccol];
+          const double* xr = Xs + (kb * 16 + s4 * 4 + krow) * kBLdx + col0;
+          const double x0 = xr[0], x1 = xr[16];
 #pragma unroll
-          for (int t = 0; t < NMT; ++t) {
-            if (TRANS) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, wc[s4][t], acc[t], 0, 0, 0);
-            else acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(wc[s4][t], xv, acc[t], 0, 0, 0);
+          for (int t = 0; t < kH; ++t) {
+            if (TRANS) {
+              acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, wc[s4][t], acc[t][0], 0, 0, 0);
+              acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, wc[s4][t], acc[t][1], 0, 0, 0);
+            } else {
+              acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(wc[s4][t], x0, acc[t][0], 0, 0, 0);
+              acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(wc[s4][t], x1, acc[t][1], 0, 0, 0);
+            }
           }
         }
         if (kb + 1 < NMT) {
 #pragma unroll
           for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-            for (int t = 0; t < NMT; ++t) wc[s4][t] = wn[s4][t];
+            for (int t = 0; t < kH; ++t) wc[s4][t] = wn[s4][t];
         }
       }
     };
     gemm(W);
     if (FUSED) {
-      const int cc = c0 + ccol;
-      const double ls = B.lam_s[min(cc, ncols - 1)];
+      double ls[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) ls[q] = B.lam_s[min(c0 + col0 + 16 * q, ncols - 1)];
       __syncthreads();
 #pragma unroll
-      for (int t = 0; t < NMT; ++t)
+      for (int t = 0; t < kH; ++t) {
+        if (wr * kH + t >= NMT) continue;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = t * 16 + (lane >> 4) + 4 * r;
-          const double q = acc[t][r] / (B.lam_t[min(i, n - 1)] + ls);
-          Xs[i * kBLdx + ccol] = i < n ? q : 0.0;
-        }
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = (wr * kH + t) * 16 + (lane >> 4) + 4 * r;
+            const double v2 = acc[t][q][r] / (B.lam_t[min(i, n - 1)] + ls[q]);
+            Xs[i * kBLdx + col0 + 16 * q] = i < n ? v2 : 0.0;
+          }
+      }
       __syncthreads();
       gemm(B.Ab[mode]);
     }
     double ds = 0.0;
 #pragma unroll
-    for (int t = 0; t < NMT; ++t)
+    for (int t = 0; t < kH; ++t) {
+      if (wr * kH + t >= NMT) continue;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int i, cc;
-        if (TRANS) { cc = c0 + wave * 16 + (lane >> 4) + 4 * r; i = t * 16 + (lane & 15); }
-        else { cc = c0 + ccol; i = t * 16 + (lane >> 4) + 4 * r; }
-        if (cc < ncols && i < n) {
-          const size_t o = (size_t)base(cc) + (size_t)i * L;
-          Yp[o] = acc[t][r];
-          if (DOT) ds += acc[t][r] * dotv[B.off + o];
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int i, cc;
+          if (TRANS) { cc = c0 + wq * 32 + 16 * q + (lane >> 4) + 4 * r; i = (wr * kH + t) * 16 + (lane & 15); }
+          else { cc = c0 + col0 + 16 * q; i = (wr * kH + t) * 16 + (lane >> 4) + 4 * r; }
+          if (cc < ncols && i < n) {
+            const size_t o = (size_t)base(cc) + (size_t)i * L;
+            Yp[o] = acc[t][q][r];
+            if (DOT) ds += acc[t][q][r] * dotv[B.off + o];
+          }
         }
-      }
+    }
     if (DOT) {
       const double s = bsum(ds, red);
       if (tid == 0) partials[item0 + it] = s;
