@@ -20,6 +20,7 @@
 #include <thread>
 #include <vector>
 
+#include "stls_buf.h"
 #include "stls_internal.h"
 
 namespace stls {
@@ -266,27 +267,36 @@ __global__ __launch_bounds__(kT) void binner1_kernel(const double* __restrict__ 
 // Outer stage (last space direction and time), same streaming scheme as the
 // single-problem kernel: per item 16 inner indices x Td rows of i_d x a chunk
 // of output time slices, register window of 2P+1 slices, fused final-time
-// term and fused partial dot product y . dotv.  P: degree in space and time.
-template <int PP>
+// term and fused partial dot product y . dotv (DOT).  P: degree in space and
+// time; THREE: d = 2 (the inner stage's A, B, C), else d = 1 (x alone).
+// Slices t + 1 and t + 2 are in flight in registers while slice t is applied
+// from LDS (double buffered, one barrier per step); the dot operand of the
+// output slice travels with them.  All reads and the y store are
+// range-checked buffer accesses of the problem's own vectors, so no load is
+// consumed in the step that issues it.
+typedef __attribute__((address_space(4))) double kconst_f64;
+
+template <int PP, bool THREE, bool DOT>
 __global__ __launch_bounds__(kT) void bouter_kernel(const double* __restrict__ A, const double* __restrict__ Bi,
                                                     const double* __restrict__ C, double* __restrict__ y,
                                                     const BProb* __restrict__ P, const Item* __restrict__ items,
                                                     int nitems, const PcgScalars* __restrict__ S,
                                                     const double* __restrict__ dotv, double* __restrict__ partials) {
   constexpr int W = 2 * PP + 1;
-  constexpr int ROWS = kOMaxTd + 2 * PP;
-  __shared__ double sbuf[2][3][ROWS * kOLb];
+  constexpr int ROWS = kOMaxTd * kOSlots;  // >= Td + 2P: every thread's slots have a row
+  static_assert(kOMaxTd + 2 * PP <= ROWS, "halo rows exceed the slots");
+  constexpr int NA = THREE ? 3 : 1;
+  __shared__ double sbuf[2][NA][ROWS * kOLb];
   __shared__ double red[4];
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item I = items[it];
     if (skip(S, I.prob)) {
-      if (threadIdx.x == 0) partials[it] = 0.0;
+      if (DOT && threadIdx.x == 0) partials[it] = 0.0;
       continue;
     }
     const BProb& B = P[I.prob];
-    const int d = B.d;
-    const bool three = d == 2;
-    const int L = (d == 2) ? B.n[0] : 1;
+    const int d = THREE ? 2 : 1;
+    const int L = THREE ? B.n[0] : 1;
     const int nd = B.n[d - 1], nt = B.n[d];
     const int Td = B.Td, rows = Td + 2 * PP;
     const int td = I.idx % B.ntd, lb = (I.idx / B.ntd) % B.nlb, ch = I.idx / (B.ntd * B.nlb);
@@ -295,15 +305,21 @@ __global__ __launch_bounds__(kT) void bouter_kernel(const double* __restrict__ A
     const int l = l0 + li, id = d0 + di;
     const bool mine = di < Td && l < L && id < nd;
     const int dic = min(di, Td - 1), idc = min(id, nd - 1);
-    const size_t plane = (size_t)L * nd;
-    const double* Ap = A + B.off;
-    const double* Bp = three ? Bi + B.off : nullptr;
-    const double* Cp = three ? C + B.off : nullptr;
+    const int plane = L * nd;
+    const size_t bytes = sizeof(double) * (size_t)B.N;
+    const __amdgpu_buffer_rsrc_t rA = buf_rsrc(A + B.off, bytes);
+    const __amdgpu_buffer_rsrc_t rB = buf_rsrc(THREE ? Bi + B.off : A + B.off, bytes);
+    const __amdgpu_buffer_rsrc_t rC = buf_rsrc(THREE ? C + B.off : A + B.off, bytes);
+    const __amdgpu_buffer_rsrc_t rY = buf_rsrc(y + B.off, bytes);
+    const __amdgpu_buffer_rsrc_t rD = buf_rsrc(DOT ? dotv + B.off : A + B.off, bytes);
     const double* Md = B.M[d - 1];
     const double* Jd = B.J[d - 1];
     const double* Kd = B.K[d - 1];
-    const double* Kt = B.K[d];
-    const double* Mt = B.M[d];
+    // time band rows at a uniform index: read through the constant address
+    // space (the bands are not written by any kernel), i.e. scalar loads that
+    // do not share the vector memory counter with the prefetched slices
+    const kconst_f64* Kt = (const kconst_f64*)B.K[d];
+    const kconst_f64* Mt = (const kconst_f64*)B.M[d];
     double cm[W], cj[W], ck[W];
 #pragma unroll
     for (int o = 0; o < W; ++o) { cm[o] = Md[idc * W + o]; cj[o] = Jd[idc * W + o]; ck[o] = Kd[idc * W + o]; }
@@ -312,62 +328,88 @@ __global__ __launch_bounds__(kT) void bouter_kernel(const double* __restrict__ A
     for (int k = 0; k < W; ++k) { S1w[k] = 0.0; S2w[k] = 0.0; }
     double S3 = 0.0, ds = 0.0;
     const int tb = max(0, c0 - PP), te = c1 - 1 + PP;
-    for (int t = tb; t <= te; ++t) {
-      __syncthreads();
-      if (t < nt) {
-        for (int s = 0; s < kOSlots; ++s) {
-          const int rr = di + kOMaxTd * s;
-          const int row = d0 - PP + rr;
-          if (rr < rows) {
-            const bool ok = row >= 0 && row < nd && l < L;
-            const size_t g = (size_t)t * plane + (size_t)(ok ? row : 0) * L + (ok ? l : 0);
-            const double a = Ap[g];
-            sbuf[0][0][rr * kOLb + li] = ok ? a : 0.0;
-            if (three) {
-              const double bv = Bp[g], cv = Cp[g];
-              sbuf[0][1][rr * kOLb + li] = ok ? bv : 0.0;
-              sbuf[0][2][rr * kOLb + li] = ok ? cv : 0.0;
-            }
-          }
+    struct Slice {
+      double v[kOSlots][NA];
+      double dv;
+    };
+    // Slices past nt are read clamped and zeroed in step(); only per-lane
+    // selects here, so the loads are not split by uniform branches.
+    auto fetch = [&](int t, Slice& R) {
+      const int tc = min(t, nt - 1);
+#pragma unroll
+      for (int s = 0; s < kOSlots; ++s) {
+        const int rr = di + kOMaxTd * s;
+        const int row = d0 - PP + rr;
+        const bool ok = rr < rows && row >= 0 && row < nd && l < L;
+        const int off = ok ? (int)sizeof(double) * (tc * plane + row * L + l) : kOutOfRange;
+        R.v[s][0] = buf_load_f64(rA, off);
+        if (THREE) {
+          R.v[s][1] = buf_load_f64(rB, off);
+          R.v[s][2] = buf_load_f64(rC, off);
         }
       }
-      __syncthreads();
-      double s1 = 0.0, jA = 0.0, mB = 0.0, kC = 0.0, kA = 0.0, mC = 0.0;
-      if (t < nt) {
+      if (DOT) {
+        const int tp = min(max(t - PP, 0), nt - 1);
+        R.dv = buf_load_f64(rD, mine ? (int)sizeof(double) * (tp * plane + id * L + l) : kOutOfRange);
+      }
+    };
+    auto put = [&](int buf, const Slice& R) {
 #pragma unroll
-        for (int o = 0; o < W; ++o) {
-          const int rr = dic + o;
-          const double a = sbuf[0][0][rr * kOLb + li];
-          s1 += cm[o] * a;
-          jA += cj[o] * a;
-          kA += ck[o] * a;
-          if (three) {
-            const double bv = sbuf[0][1][rr * kOLb + li], cv = sbuf[0][2][rr * kOLb + li];
-            mB += cm[o] * bv;
-            kC += ck[o] * cv;
-            mC += cm[o] * cv;
-          }
+      for (int s = 0; s < kOSlots; ++s) {
+        const int rr = di + kOMaxTd * s;
+#pragma unroll
+        for (int q = 0; q < NA; ++q) sbuf[buf][q][rr * kOLb + li] = R.v[s][q];
+      }
+    };
+    double dvc = 0.0;  // dot operand at slice t - PP
+    auto step = [&](int cur, Slice& R, int t) {
+      double s1 = 0.0, jA = 0.0, mB = 0.0, kC = 0.0, kA = 0.0, mC = 0.0;
+#pragma unroll
+      for (int o = 0; o < W; ++o) {
+        const int rr = dic + o;
+        const double a = sbuf[cur][0][rr * kOLb + li];
+        s1 += cm[o] * a;
+        jA += cj[o] * a;
+        kA += ck[o] * a;
+        if (THREE) {
+          const double bv = sbuf[cur][1][rr * kOLb + li], cv = sbuf[cur][2][rr * kOLb + li];
+          mB += cm[o] * bv;
+          kC += ck[o] * cv;
+          mC += cm[o] * cv;
         }
       }
       if (t == nt - 1) S3 = B.kw * (kA + mC);
+      const bool live = t < nt;
 #pragma unroll
       for (int k = 0; k < W - 1; ++k) { S1w[k] = S1w[k + 1]; S2w[k] = S2w[k + 1]; }
-      S1w[W - 1] = s1;
-      S2w[W - 1] = B.k2 * (jA + mB + 2.0 * kC);
-      const int tp = t - PP;
-      if (tp >= c0 && tp < c1) {
-        double v = 0.0;
+      S1w[W - 1] = live ? s1 : 0.0;
+      S2w[W - 1] = live ? B.k2 * (jA + mB + 2.0 * kC) : 0.0;
+      const int tp = t - PP, tpc = min(max(tp, 0), nt - 1);
+      const bool out = tp >= c0 && tp < c1;
+      double v = 0.0;
 #pragma unroll
-        for (int k = 0; k < W; ++k) v += Kt[tp * W + k] * S1w[k] + Mt[tp * W + k] * S2w[k];
-        if (tp == nt - 1) v += S3;
-        if (mine) {
-          const size_t g = (size_t)tp * plane + (size_t)id * L + l;
-          y[B.off + g] = v;
-          if (dotv) ds += v * dotv[B.off + g];
-        }
-      }
+      for (int k = 0; k < W; ++k) v += Kt[tpc * W + k] * S1w[k] + Mt[tpc * W + k] * S2w[k];
+      if (tp == nt - 1) v += S3;
+      buf_store(v, rY, out && mine ? (int)sizeof(double) * (tpc * plane + id * L + l) : kOutOfRange);
+      if (DOT) ds += out && mine ? v * dvc : 0.0;
+      put(cur ^ 1, R);  // slice t + 1
+      if (DOT) dvc = R.dv;
+      fetch(t + 3, R);
+      __syncthreads();
+    };
+    Slice R0, R1;
+    __syncthreads();  // previous item's LDS reads are done
+    fetch(tb, R0);
+    put(0, R0);
+    if (DOT) dvc = R0.dv;
+    fetch(tb + 1, R0);
+    fetch(tb + 2, R1);
+    __syncthreads();
+    for (int t = tb; t <= te; t += 2) {
+      step(0, R0, t);
+      if (t + 1 <= te) step(1, R1, t + 1);
     }
-    if (dotv) {
+    if (DOT) {
       const double s = bsum(ds, red);
       if (threadIdx.x == 0) partials[it] = s;
     }
@@ -645,6 +687,12 @@ int bprec(stls_batch_ctx* B, const double* r, double* s, const double* dotv) {
   return STLS_OK;
 }
 
+template <int PP>
+auto outer_instance(bool three, bool dot) {
+  return three ? (dot ? bouter_kernel<PP, true, true> : bouter_kernel<PP, true, false>)
+               : (dot ? bouter_kernel<PP, false, true> : bouter_kernel<PP, false, false>);
+}
+
 int bmatvec(stls_batch_ctx* B, const double* x, double* y, const double* dotv) {
   hipStream_t st = B->stream;
   const double* A = x;
@@ -679,12 +727,12 @@ int bmatvec(stls_batch_ctx* B, const double* x, double* y, const double* dotv) {
     void (*kern)(const double*, const double*, const double*, double*, const BProb*, const Item*, int,
                  const PcgScalars*, const double*, double*) = nullptr;
     switch (B->outer_p[g]) {
-      case 1: kern = bouter_kernel<1>; break;
-      case 2: kern = bouter_kernel<2>; break;
-      case 3: kern = bouter_kernel<3>; break;
-      case 4: kern = bouter_kernel<4>; break;
-      case 5: kern = bouter_kernel<5>; break;
-      case 6: kern = bouter_kernel<6>; break;
+      case 1: kern = outer_instance<1>(B->d == 2, dotv != nullptr); break;
+      case 2: kern = outer_instance<2>(B->d == 2, dotv != nullptr); break;
+      case 3: kern = outer_instance<3>(B->d == 2, dotv != nullptr); break;
+      case 4: kern = outer_instance<4>(B->d == 2, dotv != nullptr); break;
+      case 5: kern = outer_instance<5>(B->d == 2, dotv != nullptr); break;
+      case 6: kern = outer_instance<6>(B->d == 2, dotv != nullptr); break;
       default: set_error("batch degree not supported"); return STLS_EINVAL;
     }
     hipLaunchKernelGGL(kern, dim3(grid_items(L.count)), dim3(kT), 0, st, A, Bv, C, y, B->desc, L.dev, L.count, B->S,

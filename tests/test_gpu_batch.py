@@ -38,6 +38,17 @@ def _batch(specs):
     return stls.Batch(probs), probs
 
 
+def _power(apply, n, its=60):
+    """Largest eigenvalue of a symmetric positive definite operator (power iteration)."""
+    v = np.random.default_rng(5).standard_normal(n)
+    lam = 0.0
+    for _ in range(its):
+        w = apply(v)
+        lam = float(np.linalg.norm(w) / np.linalg.norm(v))
+        v = w / np.linalg.norm(w)
+    return lam
+
+
 def _single(B, i, probs):
     knots, degs, kappa = probs[i]
     return stls.Solver(knots, degs, kappa=kappa)
@@ -79,6 +90,55 @@ def test_batched_solve_matches_single_and_oracle():
     xr, info = opcg.pcg(lambda v: osys.vec(P.matvec(v)), lambda v: osys.vec(fdo.apply(v)), bi, 1e-8)
     assert abs(its[i] - info["iters"]) <= 1
     assert rel_err(to_host(x[off[i]:off[i + 1]]), xr) < 1e-6
+
+
+SMALL_D1 = [
+    ((9, 8), 2, 0.5),
+    ((20, 13), 3, 1.7),
+    ((14, 30), 6, 0.2),
+    ((40, 35), 4, 3.0),
+]
+
+
+def test_d1_batch_matches_single_problems():
+    """d = 1 batches (the outer stage reads x alone), degrees up to 6: the
+    operators agree with the standalone ones (matvec) and the oracle (FD),
+    solves with the standalone solves."""
+    probs = []
+    for nel, p, kappa in SMALL_D1:
+        knots, degs = problem_knots(1, list(nel), p)
+        probs.append((knots, degs, kappa))
+    assert stls is not None, "libstls.so is not built"
+    B = stls.Batch(probs)
+    off = B.offsets
+    x = to_dev(uniform_pm1(B.total, 64))
+    y = B.matvec(x)
+    s = B.prec_apply(x)
+    for i, (knots, degs, kappa) in enumerate(probs):
+        S = stls.Solver(knots, degs, kappa=kappa)
+        xi = x[off[i]:off[i + 1]].contiguous()
+        assert rel_err(to_host(y[off[i]:off[i + 1]]), to_host(S.matvec(xi))) < 1e-13
+        si = to_host(s[off[i]:off[i + 1]])
+        # same host factors as the standalone handle: kernels differ only in rounding order
+        assert rel_err(si, to_host(S.prec_apply(xi))) < 1e-12
+        # against the oracle's own eigendecomposition: backward error at rounding
+        # level, forward difference within 10 eps cond(P)
+        P = osys.Problem(knots, degs, kappa=kappa)
+        r = to_host(xi)
+        Pv = lambda v: osys.vec(P.prec_matvec(v))
+        fdo = ofd.FD(P)
+        normP = _power(Pv, P.ndof)
+        cond = normP * _power(lambda v: osys.vec(fdo.apply(v)), P.ndof)
+        assert np.linalg.norm(Pv(si) - r) / (normP * np.linalg.norm(si)) < 1e-14
+        assert rel_err(si, osys.vec(fdo.apply(r))) < max(1e-12, 10 * np.finfo(float).eps * cond)
+    b = to_dev(uniform_pm1(B.total, 65))
+    xb, its, rels = B.solve(b, rtol=1e-8, maxit=300)
+    assert all(r <= 1e-8 for r in rels)
+    for i, (knots, degs, kappa) in enumerate(probs):
+        S = stls.Solver(knots, degs, kappa=kappa)
+        xs, it_s, _ = S.solve(b[off[i]:off[i + 1]].contiguous(), rtol=1e-8)
+        assert abs(its[i] - it_s) <= 1
+        assert rel_err(to_host(xb[off[i]:off[i + 1]]), to_host(xs)) < 1e-7
 
 
 def test_full_uneven_batch_converges():
