@@ -32,7 +32,7 @@ constexpr int kBCols = 64;            // FD panel width
 constexpr int kBLdx = kBCols + 1;     // panel LDS row stride (static LDS stays below 64 KB)
 constexpr int kBNM = 7;               // max 16-row tiles per direction (n <= 112)
 constexpr int kVecChunk = 4096;       // elements per vector work item
-constexpr int kInChunk = 1024;        // elements per inner-stage work item
+constexpr int kInSteps = 8;           // column steps per inner-stage work item
 constexpr int kOLb = 16, kOMaxTd = 16, kOSlots = 2;
 
 typedef double d4b_t __attribute__((ext_vector_type(4)));
@@ -224,10 +224,12 @@ __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, d
 }
 
 // Inner stage of the matvec for d = 2: A = M1 x, B = J1 x, C = K1 x along the
-// contiguous columns of n1 entries (chunks of kInChunk elements), for the
-// problems of degree PP: the 2PP+1 taps are unrolled with clamped columns
-// (band entries outside the matrix are stored as zeros, so the clamped
-// reads add nothing).
+// contiguous columns of n1 entries, for the problems of degree PP.  Thread t
+// of a workgroup owns row i = t mod n1 of the three banded operators (its
+// 3 (2PP+1) band entries stay in registers for the whole item) and column
+// lane t / n1 of G = kT / n1; an item is kInSteps column steps of G columns.
+// The 2PP+1 taps are unrolled with clamped columns (band entries outside the
+// matrix are stored as zeros, so the clamped reads add nothing).
 template <int PP>
 __global__ __launch_bounds__(kT) void binner1_kernel(const double* __restrict__ x, double* __restrict__ A,
                                                      double* __restrict__ Bo, double* __restrict__ C,
@@ -238,28 +240,45 @@ __global__ __launch_bounds__(kT) void binner1_kernel(const double* __restrict__ 
     const Item I = items[it];
     if (skip(S, I.prob)) continue;
     const BProb& B = P[I.prob];
-    const int n1 = B.n[0];
-    const double* __restrict__ Mb = B.M[0];
-    const double* __restrict__ Jb = B.J[0];
-    const double* __restrict__ Kb = B.K[0];
-    const long long off = B.off;
-    const int e0 = I.idx * kInChunk, e1 = min(B.N, e0 + kInChunk);
-    const double* xp = x + off;
-    for (int e = e0 + threadIdx.x; e < e1; e += kT) {
-      const int i = e % n1, col0 = e - i;
+    const int n1 = B.n[0], G = kT / n1, ncols = B.N / n1;
+    const int t = threadIdx.x, cg = t / n1;
+    const int i = min(t - cg * n1, n1 - 1);
+    const bool act = cg < G;
+    double cm[BW], cj[BW], ck[BW];
+#pragma unroll
+    for (int o = 0; o < BW; ++o) {
+      cm[o] = B.M[0][i * BW + o];
+      cj[o] = B.J[0][i * BW + o];
+      ck[o] = B.K[0][i * BW + o];
+    }
+    int tap[BW];  // clamped row offsets of the window
+#pragma unroll
+    for (int o = 0; o < BW; ++o) tap[o] = (int)sizeof(double) * min(max(i + o - PP, 0), n1 - 1);
+    const size_t bytes = sizeof(double) * (size_t)B.N;
+    const __amdgpu_buffer_rsrc_t rX = buf_rsrc(x + B.off, bytes);
+    const __amdgpu_buffer_rsrc_t rA = buf_rsrc(A + B.off, bytes);
+    const __amdgpu_buffer_rsrc_t rB = buf_rsrc(Bo + B.off, bytes);
+    const __amdgpu_buffer_rsrc_t rC = buf_rsrc(C + B.off, bytes);
+    const int cb = I.idx * G * kInSteps + cg;
+#pragma unroll 2
+    for (int s = 0; s < kInSteps; ++s) {
+      const int c = cb + s * G;
+      const bool ok = act && c < ncols;
+      const int colb = (int)sizeof(double) * min(c, ncols - 1) * n1;
       double v[BW];
 #pragma unroll
-      for (int o = 0; o < BW; ++o) v[o] = xp[col0 + min(max(i + o - PP, 0), n1 - 1)];
-      double a = 0.0, b = 0.0, c = 0.0;
+      for (int o = 0; o < BW; ++o) v[o] = buf_load_f64(rX, ok ? colb + tap[o] : kOutOfRange);
+      double a = 0.0, b = 0.0, cc = 0.0;
 #pragma unroll
       for (int o = 0; o < BW; ++o) {
-        a += Mb[i * BW + o] * v[o];
-        b += Jb[i * BW + o] * v[o];
-        c += Kb[i * BW + o] * v[o];
+        a += cm[o] * v[o];
+        b += cj[o] * v[o];
+        cc += ck[o] * v[o];
       }
-      A[off + e] = a;
-      Bo[off + e] = b;
-      C[off + e] = c;
+      const int so = ok ? colb + (int)sizeof(double) * i : kOutOfRange;
+      buf_store(a, rA, so);
+      buf_store(b, rB, so);
+      buf_store(cc, rC, so);
     }
   }
 }
@@ -837,7 +856,10 @@ int stls_batch_setup(int nprob, int d, const int* nknots, const double* const* k
     P.Tc = nt;
     cnt_outer[i] = P.nlb * P.ntd * P.nchunk;
     cnt_vec[i] = (P.N + kVecChunk - 1) / kVecChunk;
-    cnt_in[i] = (P.N + kInChunk - 1) / kInChunk;
+    {
+      const int G = kT / P.n[0], ncols = P.N / P.n[0];  // n[0] <= 112: G >= 2
+      cnt_in[i] = (ncols + G * kInSteps - 1) / (G * kInSteps);
+    }
     B->off[i + 1] = B->off[i] + P.N;
   }
   B->total = B->off[nprob];
