@@ -198,11 +198,13 @@ def main():
 
     err_norms = gpu_error_norms(stls, torch)
     batch = gpu_batch(stls, torch)
+    lifting = gpu_lifting(stls, torch, knots, degs)
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(knots, degs, b.cpu().numpy(), res["fp64"]["iters"], N)
         err_norms["oracle_cpu"] = cpu_error_norms()
+        lifting["oracle_cpu"] = cpu_lifting(knots, degs)
 
     t_mixed, t_fp64 = res[mixed]["time_s"], res["fp64"]["time_s"]
     out = {
@@ -232,6 +234,7 @@ def main():
         "diag_scaled_prec": scaled,
         "error_norms": err_norms,
         "batch": batch,
+        "lifting": lifting,
         "setup_s": setup_s,
         "roofline": roofline,
         "roofline_note": "kernel durations from HIP events recorded around every launch on the solver's "
@@ -304,6 +307,52 @@ def gpu_batch(stls, torch, steps=3):
             "total_dof": int(B.total), "seconds": dt, "dof_per_s": B.total / dt, "max_iters": int(max(its)),
             "iteration_ms": dt / max(its) * 1e3, "graph_replay": bool(B.graph_used), "setup_s": setup_s,
             "max_relres": float(max(rels))}
+
+
+def gpu_lifting(stls, torch, knots, degs, reps=20):
+    """Lifting of non-zero initial data (§2) on the benchmark shape: the
+    coupling F -= a(u0_h b_1, B_i) (stls_lift_initial) and the assembly of
+    the full-time coefficients (stls_lift_combine), u0 U[-1, 1] (seed 1812).
+    Algorithmic bytes: read u0, read and write the first p_t time slices of F."""
+    from stls_inputs import uniform_pm1
+    S = stls.Solver(knots, degs)
+    u0 = torch.as_tensor(uniform_pm1(S.ns, 1812)).cuda()
+    F = torch.as_tensor(uniform_pm1(S.ndof, 1813)).cuda()
+    w = torch.zeros(S.ndof, dtype=torch.float64, device="cuda")
+    S.lift_initial(u0, F)
+    u = S.lift_combine(u0, w)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        S.lift_initial(u0, F)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    t = time.perf_counter()
+    for _ in range(reps):
+        S.lift_combine(u0, w, out=u)
+    torch.cuda.synchronize()
+    dc = (time.perf_counter() - t) / reps
+    pt = degs[-1]
+    nbytes = 8 * S.ns * (1 + 2 * min(pt, S.shape[-1]))
+    d = len(knots) - 1
+    log(f"lifting: coupling {dt*1e6:.1f} us, combine {dc*1e6:.1f} us")
+    return {"workload": "d=3, p=4, 48 elements/dir: u0 on the 50^3 spatial coefficients, F of 6,375,000",
+            "coupling_s": dt, "combine_s": dc, "algorithmic_bytes": nbytes,
+            "coupling_GB_per_s": nbytes / dt / 1e9, "kronecker_terms": 1 + d + d * (d - 1) // 2,
+            "launches": (1 + d + d * (d - 1) // 2) * (d + 1)}
+
+
+def cpu_lifting(knots, degs):
+    """The oracle's coupling (numpy, host cores) on the same shape."""
+    from oracle import lift, system
+    from stls_inputs import uniform_pm1
+    P = system.Problem(knots, degs)
+    u0 = uniform_pm1(int(P.ndof // P.shape[-1]), 1812)
+    t = time.perf_counter()
+    lift.initial_coupling(P, u0)
+    dt = time.perf_counter() - t
+    log(f"cpu lifting: {dt:.3f} s")
+    return {"kind": "oracle", "coupling_s": dt}
 
 
 def cpu_error_norms(nel=32):

@@ -202,6 +202,29 @@ int stls_load_apply(stls_handle h, const double* f, double* F);
 /* gf = B_kappa^T l: l ndof doubles, gf nfull doubles. */
 int stls_load_apply_T(stls_handle h, const double* l, double* gf);
 
+/* ------------------------------------------------------------------------
+ * Non-zero initial data by lifting (§2, the paragraph after the parabolic
+ * regularity theorem; least-squares form §3.2).  An initial value u0 in
+ * H^1_0 is represented by its coefficients u0_h over the restricted spatial
+ * space (ns doubles, colexicographic, FP64, device), carried by the first
+ * time B-spline b_1.  The solution is u_h = w_h + u0_h b_1, where w_h in the
+ * zero-data space solves A w = F - a(u0_h b_1, B_i).  Stream-ordered and
+ * asynchronous.  The full-space workspace of the differentiation operators
+ * is allocated on first use.
+ * ------------------------------------------------------------------------ */
+
+/* F -= a(u0_h b_1, B_i) for every restricted B_i, i.e. the system matrix with
+ * each time factor replaced by its column of b_1 (int b_j' b_1', int b_j b_1;
+ * the final-time term vanishes since b_1(T) = 0).  Only the first
+ * min(p_t, n_t) time slices of F change.  u0: ns doubles; F: ndof doubles,
+ * updated in place.  STLS_EINVAL for NULL arguments. */
+int stls_lift_initial(stls_handle h, const double* u0, double* F);
+
+/* u = [u0_h, w_h]: the coefficients of u_h over every time function, time
+ * slowest (ns * (n_t + 1) doubles); u0: ns doubles, w: ndof doubles.  The
+ * buffers must not overlap.  STLS_EINVAL for NULL arguments. */
+int stls_lift_combine(stls_handle h, const double* u0, const double* w, double* u);
+
 /* y = (M_t (x) M_s) x, the Gram matrix of L2(space x time) on the discrete
  * space (x, y: ndof doubles, must differ). */
 int stls_mass_apply(stls_handle h, const double* x, double* y);

@@ -22,6 +22,7 @@ __all__ = [
     "stls_setup", "stls_destroy", "stls_get_shape", "stls_get_factor", "stls_set_kappa",
     "stls_set_fd_precision", "stls_set_fd_scaling", "stls_prec_apply", "stls_matvec", "stls_pcg_solve",
     "stls_pcg_history", "stls_norm_points", "stls_error_norms", "stls_set_profiling", "stls_profile", "stls_profile_reset",
+    "stls_lift_initial", "stls_lift_combine",
     "Solver",
 ]
 
@@ -67,6 +68,8 @@ _sig = {
     "stls_get_forcing_shape": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, ctypes.POINTER(ctypes.c_int64)]),
     "stls_load_apply": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
     "stls_load_apply_T": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
+    "stls_lift_initial": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
+    "stls_lift_combine": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_dbl_p]),
     "stls_mass_apply": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
     "stls_dkappa": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_dbl_p, ctypes.POINTER(ctypes.c_double)]),
     "stls_dot": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
@@ -226,6 +229,15 @@ def stls_load_apply(h, nfull, ndof, f, F):
 
 def stls_load_apply_T(h, nfull, ndof, lam, gf):
     _check(_lib.stls_load_apply_T(h, _dev_ptr(lam, ndof, "l"), _dev_ptr(gf, nfull, "gf")), "stls_load_apply_T")
+
+
+def stls_lift_initial(h, ns, ndof, u0, F):
+    _check(_lib.stls_lift_initial(h, _dev_ptr(u0, ns, "u0"), _dev_ptr(F, ndof, "F")), "stls_lift_initial")
+
+
+def stls_lift_combine(h, ns, ndof, u0, w, u):
+    _check(_lib.stls_lift_combine(h, _dev_ptr(u0, ns, "u0"), _dev_ptr(w, ndof, "w"), _dev_ptr(u, ns + ndof, "u")),
+           "stls_lift_combine")
 
 
 def stls_mass_apply(h, ndof, x, y):
@@ -457,6 +469,24 @@ class Solver:
         gf = torch.empty(nf, dtype=torch.float64, device="cuda") if out is None else out
         stls_load_apply_T(self._h, nf, self.ndof, lam, gf)
         return gf
+
+    # --- lifting of non-zero initial data ---------------------------------
+    @property
+    def ns(self):
+        return self.ndof // self.shape[-1]
+
+    def lift_initial(self, u0, F):
+        """F -= a(u0_h b_1, B_i) in place (u0: restricted spatial coefficients
+        of the initial value); returns F."""
+        stls_lift_initial(self._h, self.ns, self.ndof, u0, F)
+        return F
+
+    def lift_combine(self, u0, w, out=None):
+        """Coefficients over every time function: [u0, w] (time slowest)."""
+        import torch
+        u = torch.empty(self.ns + self.ndof, dtype=torch.float64, device="cuda") if out is None else out
+        stls_lift_combine(self._h, self.ns, self.ndof, u0, w, u)
+        return u
 
     def mass_apply(self, x, out=None):
         y = self._empty() if out is None else out

@@ -159,6 +159,44 @@ std::vector<std::pair<double, std::vector<Fac>>> load_terms(stls_ctx* h, bool tr
   return terms;
 }
 
+// Terms of a(u0_h b_1, B_i) for initial data u0_h (restricted spatial
+// coefficients) on the first time function b_1 (lifting, §2; least-squares
+// form §3.2).  For a trial function that vanishes on the spatial boundary the
+// spatial integrations by parts of the system matrix hold, and the time one
+// leaves [b_1 b_j] from 0 to T, which is zero for the restricted b_j; so the
+// coupling is the system matrix with each time factor replaced by its
+// column of the first function: K_t -> int b_j' b_1', M_t -> int b_j b_1,
+// W_t -> b_j(T) b_1(T) = 0.  J_s = sum_k J_k + 2 sum_{k<l} K_k K_l (other
+// modes M), as in the matvec.  The time factor maps a mode of size 1 (the
+// coefficient of b_1) to the first min(p_t, n_t) restricted time rows, the
+// only ones whose support meets b_1's.
+std::vector<std::pair<double, std::vector<Fac>>> lift_terms(stls_ctx* h) {
+  const int d = h->d;
+  const DevDir& T = h->dd[d];
+  auto tcol = [&](const double* band) { return Fac{band, T.p, 1, 0, 1, std::min(T.p, T.n)}; };
+  auto S = [&](int k, const double* band) { return sq(h->dd[k], band); };
+  std::vector<std::pair<double, std::vector<Fac>>> terms;
+  std::vector<Fac> f0;
+  for (int k = 0; k < d; ++k) f0.push_back(S(k, h->dd[k].M));
+  f0.push_back(tcol(T.Kbar));
+  terms.push_back({-1.0, f0});
+  const double k2 = h->kappa * h->kappa;
+  for (int k = 0; k < d; ++k) {
+    std::vector<Fac> f;
+    for (int m = 0; m < d; ++m) f.push_back(S(m, m == k ? h->dd[m].J : h->dd[m].M));
+    f.push_back(tcol(T.Mbar));
+    terms.push_back({-k2, f});
+  }
+  for (int k = 0; k < d; ++k)
+    for (int l = k + 1; l < d; ++l) {
+      std::vector<Fac> f;
+      for (int m = 0; m < d; ++m) f.push_back(S(m, (m == k || m == l) ? h->dd[m].K : h->dd[m].M));
+      f.push_back(tcol(T.Mbar));
+      terms.push_back({-2.0 * k2, f});
+    }
+  return terms;
+}
+
 }  // namespace
 
 }  // namespace stls
@@ -188,6 +226,23 @@ int stls_load_apply(stls_handle h, const double* f, double* F) {
     first = false;
   }
   return STLS_OK;
+}
+
+int stls_lift_initial(stls_handle h, const double* u0, double* F) {
+  if (!h || !u0 || !F) { set_error("bad handle or pointers"); return STLS_EINVAL; }
+  int st = ensure_diff_operands(h);
+  if (st) return st;
+  for (auto& t : lift_terms(h))
+    if ((st = apply_chain(h, u0, F, t.second, t.first, true, h->ftmp[0], h->ftmp[1]))) return st;
+  return STLS_OK;
+}
+
+int stls_lift_combine(stls_handle h, const double* u0, const double* x, double* u) {
+  if (!h || !u0 || !x || !u) { set_error("bad handle or pointers"); return STLS_EINVAL; }
+  hipError_t e = hipMemcpyAsync(u, u0, sizeof(double) * (size_t)h->ns, hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(u + h->ns, x, sizeof(double) * (size_t)h->ndof, hipMemcpyDeviceToDevice, h->stream);
+  return e == hipSuccess ? STLS_OK : hip_fail(e, "hipMemcpyAsync");
 }
 
 int stls_load_apply_T(stls_handle h, const double* lam, double* gf) {

@@ -199,6 +199,7 @@ int validate_and_build_dir(const double* knots, int nknots, int p, bool is_time,
   out.Mbar.assign((size_t)n * bw, 0.0);
   out.Cbar.assign((size_t)n * bw, 0.0);
   out.Gbar.assign((size_t)n * bw, 0.0);
+  out.Kbar.assign((size_t)n * bw, 0.0);
   for (int ri = 0; ri < n; ++ri)
     for (int o = 0; o < bw; ++o) {
       const int j = ri + 1 + o - p;
@@ -207,6 +208,7 @@ int validate_and_build_dir(const double* knots, int nknots, int p, bool is_time,
       out.Mbar[(size_t)ri * bw + o] = Mf[src];
       out.Cbar[(size_t)ri * bw + o] = D1f[src];
       out.Gbar[(size_t)ri * bw + o] = G2f[src];
+      out.Kbar[(size_t)ri * bw + o] = Kf[src];
     }
   if (is_time) {
     out.J.clear();
@@ -482,6 +484,7 @@ int ensure_diff_operands(stls_ctx* h) {
     st = dev_upload(&dd.Mbar, D.Mbar.data(), D.Mbar.size(), h->stream);
     if (!st) st = dev_upload(&dd.Cbar, D.Cbar.data(), D.Cbar.size(), h->stream);
     if (!st) st = dev_upload(&dd.Gbar, D.Gbar.data(), D.Gbar.size(), h->stream);
+    if (!st) st = dev_upload(&dd.Kbar, D.Kbar.data(), D.Kbar.size(), h->stream);
   }
   if (!st && h->nfull > 2147483647LL) { set_error("forcing space too large"); st = STLS_EINVAL; }
   for (int i = 0; i < 2 && !st; ++i) {
@@ -497,7 +500,7 @@ static void free_ctx(stls_ctx* h) {
   for (int k = 0; k <= kMaxDim; ++k) {
     DevDir& dd = h->dd[k];
     void* ptrs[] = {dd.M, dd.K, dd.J, dd.Afwd64, dd.Abwd64, dd.Afwd32, dd.Abwd32, dd.Hfwd, dd.Lfwd,
-                    dd.Hbwd, dd.Lbwd, dd.lam, dd.Mbar, dd.Cbar, dd.Gbar};
+                    dd.Hbwd, dd.Lbwd, dd.lam, dd.Mbar, dd.Cbar, dd.Gbar, dd.Kbar};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
   }
