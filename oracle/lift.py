@@ -107,3 +107,100 @@ def l2_projection(P, gs):
     for v in vecs[1:]:
         out = np.multiply.outer(out, v)
     return out
+
+
+# ---------------------------------------------------------------------------
+# General data: a lifting u_B anywhere in the full spline space (non-zero
+# boundary coefficients in space and/or the initial time coefficients).
+# For such a trial function the spatial integrations by parts behind the
+# system matrix leave boundary terms, so a(u_B, B_i) is assembled from the
+# four products of the least-squares form directly:
+#   int int d_t u d_t v            -> K_t (x) M_s
+#   kappa^2 int int Lap u Lap v    -> M_t (x) sum_{k,l} int d_kk u d_ll v
+#   -kappa int int d_t u Lap v     -> (int b_i b'_j)_t (x) sum_k (int b''_i b_j)_k
+#   -kappa int int Lap u d_t v     -> (int b'_i b_j)_t (x) sum_k (int b_i b''_j)_k
+# with every factor over test functions i (rows) and trial functions j
+# (columns) of the full space; the rows are then restricted.
+
+def _full_factors(xi, p):
+    """Full m x m matrices, rows test i, columns trial j: M, K (b' b'),
+    J (b'' b''), Gt (int b''_i b_j: test second derivative), Gs (int b_i
+    b''_j: trial second derivative), Ct (int b'_i b_j: test derivative),
+    Cs (int b_i b'_j: trial derivative)."""
+    x, w = assemble.gauss_points(xi, p + 1)
+    B = eval_basis_points(xi, p, x, nder=2)
+    b0, b1, b2 = B[0], B[1], B[2]
+    ip = lambda a, b: a.T @ (w[:, None] * b)
+    return dict(M=ip(b0, b0), K=ip(b1, b1), J=ip(b2, b2), Gt=ip(b2, b0), Gs=ip(b0, b2),
+                Ct=ip(b1, b0), Cs=ip(b0, b1))
+
+
+def full_terms(P):
+    """(coefficient, factors per mode, time last) of a(u, B_i) over the full
+    space, before the restriction of the rows."""
+    d, kap = P.d, P.kappa
+    S = [_full_factors(P.knots[k], P.degrees[k]) for k in range(d)]
+    T = _full_factors(P.knots[d], P.degrees[d])
+    terms = [(1.0, [S[k]["M"] for k in range(d)] + [T["K"]])]
+    for k in range(d):
+        for l in range(d):
+            fac = [S[m]["M"] for m in range(d)]
+            if k == l:
+                fac[k] = S[k]["J"]
+            else:
+                fac[k] = S[k]["Gs"]  # trial function differentiated twice in x_k
+                fac[l] = S[l]["Gt"]  # test function differentiated twice in x_l
+            terms.append((kap * kap, fac + [T["M"]]))
+    for k in range(d):
+        fac = [S[m]["Gt"] if m == k else S[m]["M"] for m in range(d)]
+        terms.append((-kap, fac + [T["Cs"]]))
+    for k in range(d):
+        fac = [S[m]["Gs"] if m == k else S[m]["M"] for m in range(d)]
+        terms.append((-kap, fac + [T["Ct"]]))
+    return terms
+
+
+def _restricted_rows(P):
+    d = P.d
+    idx = [assemble.space_index(num_basis(P.knots[k], P.degrees[k])) for k in range(d)]
+    idx.append(assemble.time_index(num_basis(P.knots[d], P.degrees[d])))
+    return np.ix_(*idx)
+
+
+def general_coupling(P, UB):
+    """a(u_B, B_i) for every restricted B_i; UB over the full space
+    (shape P.full_shape), result of shape P.shape."""
+    UB = np.asarray(UB, dtype=float).reshape(P.full_shape, order="F")
+    full = sum(c * kron_apply(f, UB) for c, f in full_terms(P))
+    return full[_restricted_rows(P)]
+
+
+def embed(P, W):
+    """The restricted coefficients W placed in the full space (zeros on the
+    boundary and initial coefficients)."""
+    out = np.zeros(P.full_shape)
+    out[_restricted_rows(P)] = np.asarray(W, dtype=float).reshape(P.shape, order="F")
+    return out
+
+
+def full_projection(P, gs, h):
+    """L^2 projection of u = prod_k g_k(x_k) h(t) onto the full space:
+    (M_1^-1 g_1) x ... x (M_d^-1 g_d) x (M_t^-1 h), full mass matrices."""
+    vecs = []
+    for k in range(P.d + 1):
+        xi, p = P.knots[k], P.degrees[k]
+        f = gs[k] if k < P.d else h
+        m = num_basis(xi, p)
+        rhs = assemble.load_1d(xi, p, f, 0, np.arange(m))
+        vecs.append(np.linalg.solve(_full_factors(xi, p)["M"], rhs))
+    out = vecs[0]
+    for v in vecs[1:]:
+        out = np.multiply.outer(out, v)
+    return out
+
+
+def boundary_part(P, U):
+    """U (full space) with its restricted coefficients set to zero."""
+    out = np.array(U, dtype=float).reshape(P.full_shape, order="F")
+    out[_restricted_rows(P)] = 0.0
+    return out

@@ -14,14 +14,17 @@ from .bspline import eval_basis_points, num_basis
 from .system import mode_product
 
 
-def _grid(knots, degrees, full_time=False):
+def _grid(knots, degrees, full_time=False, full_space=False):
     d = len(knots) - 1
     pts, wts, mats = [], [], []
     for k in range(d + 1):
         x, w = gauss_points(knots[k], degrees[k] + 3)
         B = eval_basis_points(knots[k], degrees[k], x, nder=2)
         m = num_basis(knots[k], degrees[k])
-        idx = space_index(m) if k < d else (np.arange(m) if full_time else time_index(m))
+        if k < d:
+            idx = np.arange(m) if full_space else space_index(m)
+        else:
+            idx = np.arange(m) if full_time else time_index(m)
         pts.append(x)
         wts.append(w)
         mats.append(B[:, :, idx])  # (3, nq, n)
@@ -35,11 +38,12 @@ def _eval(coef, mats, ders):
     return X
 
 
-def error_norms(coef, knots, degrees, exact, kappa=1.0, full_time=False):
+def error_norms(coef, knots, degrees, exact, kappa=1.0, full_time=False, full_space=False):
     """Relative errors of u_h against ``exact``.
 
-    ``coef`` is indexed by the restricted spaces, or with ``full_time`` by
-    every time function (the first one carries non-zero initial data).
+    ``coef`` is indexed by the restricted spaces; with ``full_time`` by every
+    time function (the first one carries non-zero initial data), with
+    ``full_space`` by every spatial function (boundary data).
 
     ``exact`` is a dict of callables on meshgrid arrays (x_1, .., x_d, t):
     'u', 'ut' (time derivative), 'lap' (spatial Laplacian) and 'grad'
@@ -48,7 +52,7 @@ def error_norms(coef, knots, degrees, exact, kappa=1.0, full_time=False):
     space-time H^1 norm.
     """
     d = len(knots) - 1
-    pts, wts, mats = _grid(knots, degrees, full_time)
+    pts, wts, mats = _grid(knots, degrees, full_time, full_space)
     G = np.meshgrid(*pts, indexing="ij")
     W = wts[0]
     for w in wts[1:]:
