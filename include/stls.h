@@ -225,6 +225,25 @@ int stls_lift_initial(stls_handle h, const double* u0, double* F);
  * buffers must not overlap.  STLS_EINVAL for NULL arguments. */
 int stls_lift_combine(stls_handle h, const double* u0, const double* w, double* u);
 
+/* General data: a lifting u_B anywhere in the full spline space (its
+ * boundary coefficients carry the boundary values, its first time
+ * coefficients the initial value), nfull doubles laid out as the forcing of
+ * the differentiation operators.  For such trial functions the spatial
+ * integrations by parts behind the system matrix leave boundary terms, so
+ * the least-squares form of §3.2 is assembled term by term:
+ * a(u, v) = int int (d_t u - kappa Lap u)(d_t v - kappa Lap v).
+ * F -= a(u_B, B_i) for every restricted B_i; F: ndof doubles, in place.
+ * On u_B of the zero-data space this equals the system matrix.  Entries of
+ * u_B at restricted coefficients are included like any other.
+ * STLS_EINVAL for NULL arguments. */
+int stls_lift_apply(stls_handle h, const double* ub, double* F);
+
+/* u = u_B + w placed at the restricted coefficients (restricted index i is
+ * full index i + 1 in every direction): the coefficients of u_h over the
+ * full space, nfull doubles; ub nfull, w ndof.  The buffers must not
+ * overlap.  STLS_EINVAL for NULL arguments. */
+int stls_lift_embed(stls_handle h, const double* ub, const double* w, double* u);
+
 /* y = (M_t (x) M_s) x, the Gram matrix of L2(space x time) on the discrete
  * space (x, y: ndof doubles, must differ). */
 int stls_mass_apply(stls_handle h, const double* x, double* y);

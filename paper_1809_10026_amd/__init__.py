@@ -22,7 +22,7 @@ __all__ = [
     "stls_setup", "stls_destroy", "stls_get_shape", "stls_get_factor", "stls_set_kappa",
     "stls_set_fd_precision", "stls_set_fd_scaling", "stls_prec_apply", "stls_matvec", "stls_pcg_solve",
     "stls_pcg_history", "stls_norm_points", "stls_error_norms", "stls_set_profiling", "stls_profile", "stls_profile_reset",
-    "stls_lift_initial", "stls_lift_combine",
+    "stls_lift_initial", "stls_lift_combine", "stls_lift_apply", "stls_lift_embed",
     "Solver",
 ]
 
@@ -70,6 +70,8 @@ _sig = {
     "stls_load_apply_T": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
     "stls_lift_initial": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
     "stls_lift_combine": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_dbl_p]),
+    "stls_lift_apply": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
+    "stls_lift_embed": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_dbl_p]),
     "stls_mass_apply": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
     "stls_dkappa": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_dbl_p, ctypes.POINTER(ctypes.c_double)]),
     "stls_dot": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
@@ -238,6 +240,15 @@ def stls_lift_initial(h, ns, ndof, u0, F):
 def stls_lift_combine(h, ns, ndof, u0, w, u):
     _check(_lib.stls_lift_combine(h, _dev_ptr(u0, ns, "u0"), _dev_ptr(w, ndof, "w"), _dev_ptr(u, ns + ndof, "u")),
            "stls_lift_combine")
+
+
+def stls_lift_apply(h, nfull, ndof, ub, F):
+    _check(_lib.stls_lift_apply(h, _dev_ptr(ub, nfull, "ub"), _dev_ptr(F, ndof, "F")), "stls_lift_apply")
+
+
+def stls_lift_embed(h, nfull, ndof, ub, w, u):
+    _check(_lib.stls_lift_embed(h, _dev_ptr(ub, nfull, "ub"), _dev_ptr(w, ndof, "w"), _dev_ptr(u, nfull, "u")),
+           "stls_lift_embed")
 
 
 def stls_mass_apply(h, ndof, x, y):
@@ -486,6 +497,20 @@ class Solver:
         import torch
         u = torch.empty(self.ns + self.ndof, dtype=torch.float64, device="cuda") if out is None else out
         stls_lift_combine(self._h, self.ns, self.ndof, u0, w, u)
+        return u
+
+    def lift_apply(self, ub, F):
+        """F -= a(u_B, B_i) in place for a lifting u_B over the full space
+        (boundary and initial coefficients); returns F."""
+        stls_lift_apply(self._h, self.forcing_shape[1], self.ndof, ub, F)
+        return F
+
+    def lift_embed(self, ub, w, out=None):
+        """Coefficients over the full space: u_B plus w at the restricted ones."""
+        import torch
+        nf = self.forcing_shape[1]
+        u = torch.empty(nf, dtype=torch.float64, device="cuda") if out is None else out
+        stls_lift_embed(self._h, nf, self.ndof, ub, w, u)
         return u
 
     def mass_apply(self, x, out=None):

@@ -197,6 +197,75 @@ std::vector<std::pair<double, std::vector<Fac>>> lift_terms(stls_ctx* h) {
   return terms;
 }
 
+// Terms of a(u_B, B_i) for a lifting u_B anywhere in the full space
+// (boundary and/or initial coefficients), least-squares form of §3.2
+// assembled term by term: for such a trial function the integrations by
+// parts that give the system matrix leave boundary terms.  Factors are
+// restricted (test) rows x full (trial) columns.
+//   int int d_t u d_t v          : Kbar_t (x) Mbar_s
+//   kappa^2 int int Lap u Lap v  : Mbar_t (x) (Jbar_k, or Hbar_k Gbar_l for k != l)
+//   -kappa int int d_t u Lap v   : Dbar_t (x) Gbar_k
+//   -kappa int int Lap u d_t v   : Cbar_t (x) Hbar_k
+// (other modes Mbar; G: test function differentiated twice, H: trial).
+std::vector<std::pair<double, std::vector<Fac>>> general_lift_terms(stls_ctx* h) {
+  const int d = h->d;
+  const DevDir& T = h->dd[d];
+  auto R = [&](int k, const double* band) { return rect(h->dd[k], band); };
+  const double k2 = h->kappa * h->kappa, kap = h->kappa;
+  std::vector<std::pair<double, std::vector<Fac>>> terms;
+  std::vector<Fac> f0;
+  for (int k = 0; k < d; ++k) f0.push_back(R(k, h->dd[k].Mbar));
+  f0.push_back(R(d, T.Kbar));
+  terms.push_back({1.0, f0});
+  for (int k = 0; k < d; ++k)
+    for (int l = 0; l < d; ++l) {
+      std::vector<Fac> f;
+      for (int m = 0; m < d; ++m) {
+        const DevDir& D = h->dd[m];
+        const double* b = D.Mbar;
+        if (k == l && m == k) b = D.Jbar;
+        else if (m == k) b = D.Hbar;
+        else if (m == l) b = D.Gbar;
+        f.push_back(R(m, b));
+      }
+      f.push_back(R(d, T.Mbar));
+      terms.push_back({k2, f});
+    }
+  for (int k = 0; k < d; ++k) {
+    std::vector<Fac> f;
+    for (int m = 0; m < d; ++m) f.push_back(R(m, m == k ? h->dd[m].Gbar : h->dd[m].Mbar));
+    f.push_back(R(d, T.Dbar));
+    terms.push_back({-kap, f});
+  }
+  for (int k = 0; k < d; ++k) {
+    std::vector<Fac> f;
+    for (int m = 0; m < d; ++m) f.push_back(R(m, m == k ? h->dd[m].Hbar : h->dd[m].Mbar));
+    f.push_back(R(d, T.Cbar));
+    terms.push_back({-kap, f});
+  }
+  return terms;
+}
+
+// u[full index of r] += w[r] for every restricted multi-index r: space
+// index i is full index i + 1 (the first function is dropped), time too.
+struct EmbedShape {
+  int nm;
+  int n[kMaxDim + 1], m[kMaxDim + 1];
+};
+__global__ __launch_bounds__(kT) void embed_add_kernel(const double* __restrict__ w, double* __restrict__ u,
+                                                       EmbedShape sh, long long total) {
+  for (long long e = (long long)blockIdx.x * kT + threadIdx.x; e < total; e += (long long)gridDim.x * kT) {
+    long long rest = e, f = 0, stride = 1;
+    for (int k = 0; k < sh.nm; ++k) {
+      const int i = (int)(rest % sh.n[k]);
+      rest /= sh.n[k];
+      f += (long long)(i + 1) * stride;
+      stride *= sh.m[k];
+    }
+    u[f] += w[e];
+  }
+}
+
 }  // namespace
 
 }  // namespace stls
@@ -243,6 +312,33 @@ int stls_lift_combine(stls_handle h, const double* u0, const double* x, double* 
   if (e == hipSuccess)
     e = hipMemcpyAsync(u + h->ns, x, sizeof(double) * (size_t)h->ndof, hipMemcpyDeviceToDevice, h->stream);
   return e == hipSuccess ? STLS_OK : hip_fail(e, "hipMemcpyAsync");
+}
+
+int stls_lift_apply(stls_handle h, const double* ub, double* F) {
+  if (!h || !ub || !F) { set_error("bad handle or pointers"); return STLS_EINVAL; }
+  int st = ensure_diff_operands(h);
+  if (st) return st;
+  for (auto& t : general_lift_terms(h))
+    if ((st = apply_chain(h, ub, F, t.second, -t.first, true, h->ftmp[0], h->ftmp[1]))) return st;
+  return STLS_OK;
+}
+
+int stls_lift_embed(stls_handle h, const double* ub, const double* w, double* u) {
+  if (!h || !ub || !w || !u) { set_error("bad handle or pointers"); return STLS_EINVAL; }
+  int st = ensure_diff_operands(h);
+  if (st) return st;
+  EmbedShape sh{};
+  sh.nm = h->d + 1;
+  for (int k = 0; k <= h->d; ++k) {
+    sh.n[k] = h->dd[k].n;
+    sh.m[k] = h->dd[k].m;
+  }
+  hipError_t e = hipMemcpyAsync(u, ub, sizeof(double) * (size_t)h->nfull, hipMemcpyDeviceToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  hipLaunchKernelGGL(embed_add_kernel, dim3(grid_for(h->ndof)), dim3(kT), 0, h->stream, w, u, sh,
+                     (long long)h->ndof);
+  e = hipGetLastError();
+  return e == hipSuccess ? STLS_OK : hip_fail(e, "embed_add_kernel launch");
 }
 
 int stls_load_apply_T(stls_handle h, const double* lam, double* gf) {

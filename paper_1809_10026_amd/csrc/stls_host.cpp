@@ -156,6 +156,7 @@ int validate_and_build_dir(const double* knots, int nknots, int p, bool is_time,
   const int bw = 2 * p + 1;
   std::vector<double> Mf((size_t)m * bw, 0.0), Kf((size_t)m * bw, 0.0), Jf((size_t)m * bw, 0.0);
   std::vector<double> D1f((size_t)m * bw, 0.0), G2f((size_t)m * bw, 0.0);  // int b'_i b_j, int b''_i b_j
+  std::vector<double> D0f((size_t)m * bw, 0.0), H2f((size_t)m * bw, 0.0);  // int b_i b'_j, int b_i b''_j
   std::vector<double> gx, gw;
   gauss_legendre(p + 1, gx, gw);
   for (int s = p; s < m; ++s) {
@@ -176,6 +177,8 @@ int validate_and_build_dir(const double* knots, int nknots, int p, bool is_time,
           Jf[e] += wq * v[2][r] * v[2][c];
           D1f[e] += wq * v[1][r] * v[0][c];
           G2f[e] += wq * v[2][r] * v[0][c];
+          D0f[e] += wq * v[0][r] * v[1][c];
+          H2f[e] += wq * v[0][r] * v[2][c];
         }
       }
     }
@@ -200,6 +203,9 @@ int validate_and_build_dir(const double* knots, int nknots, int p, bool is_time,
   out.Cbar.assign((size_t)n * bw, 0.0);
   out.Gbar.assign((size_t)n * bw, 0.0);
   out.Kbar.assign((size_t)n * bw, 0.0);
+  out.Jbar.assign((size_t)n * bw, 0.0);
+  out.Hbar.assign((size_t)n * bw, 0.0);
+  out.Dbar.assign((size_t)n * bw, 0.0);
   for (int ri = 0; ri < n; ++ri)
     for (int o = 0; o < bw; ++o) {
       const int j = ri + 1 + o - p;
@@ -209,6 +215,9 @@ int validate_and_build_dir(const double* knots, int nknots, int p, bool is_time,
       out.Cbar[(size_t)ri * bw + o] = D1f[src];
       out.Gbar[(size_t)ri * bw + o] = G2f[src];
       out.Kbar[(size_t)ri * bw + o] = Kf[src];
+      out.Jbar[(size_t)ri * bw + o] = Jf[src];
+      out.Hbar[(size_t)ri * bw + o] = H2f[src];
+      out.Dbar[(size_t)ri * bw + o] = D0f[src];
     }
   if (is_time) {
     out.J.clear();
@@ -485,6 +494,9 @@ int ensure_diff_operands(stls_ctx* h) {
     if (!st) st = dev_upload(&dd.Cbar, D.Cbar.data(), D.Cbar.size(), h->stream);
     if (!st) st = dev_upload(&dd.Gbar, D.Gbar.data(), D.Gbar.size(), h->stream);
     if (!st) st = dev_upload(&dd.Kbar, D.Kbar.data(), D.Kbar.size(), h->stream);
+    if (!st) st = dev_upload(&dd.Jbar, D.Jbar.data(), D.Jbar.size(), h->stream);
+    if (!st) st = dev_upload(&dd.Hbar, D.Hbar.data(), D.Hbar.size(), h->stream);
+    if (!st) st = dev_upload(&dd.Dbar, D.Dbar.data(), D.Dbar.size(), h->stream);
   }
   if (!st && h->nfull > 2147483647LL) { set_error("forcing space too large"); st = STLS_EINVAL; }
   for (int i = 0; i < 2 && !st; ++i) {
@@ -500,7 +512,7 @@ static void free_ctx(stls_ctx* h) {
   for (int k = 0; k <= kMaxDim; ++k) {
     DevDir& dd = h->dd[k];
     void* ptrs[] = {dd.M, dd.K, dd.J, dd.Afwd64, dd.Abwd64, dd.Afwd32, dd.Abwd32, dd.Hfwd, dd.Lfwd,
-                    dd.Hbwd, dd.Lbwd, dd.lam, dd.Mbar, dd.Cbar, dd.Gbar, dd.Kbar};
+                    dd.Hbwd, dd.Lbwd, dd.lam, dd.Mbar, dd.Cbar, dd.Gbar, dd.Kbar, dd.Jbar, dd.Hbar, dd.Dbar};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
   }

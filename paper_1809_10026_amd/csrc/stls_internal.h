@@ -27,7 +27,8 @@ struct Dir {
   // restricted x full rectangular bands (forcing in the full space), n x (2p+1):
   // entry (i, j) with j the full index at i*(2p+1) + (j - (i+1) + p)
   std::vector<double> Mbar, Cbar, Gbar;  // int b_i bbar_j, int b'_i bbar_j, int b''_i bbar_j
-  std::vector<double> Kbar;              // int b'_i bbar'_j (lifting of initial data)
+  std::vector<double> Kbar;              // int b'_i bbar'_j (lifting)
+  std::vector<double> Jbar, Hbar, Dbar;  // int b''_i bbar''_j, int b_i bbar''_j, int b_i bbar'_j (lifting)
   std::vector<double> U;    // n x n column-major, U^T M U = I
   std::vector<double> lam;  // generalized eigenvalues
   double wend = 0.0;        // b_{m}(1)^2 (time): the single entry of W_t
@@ -54,6 +55,9 @@ struct DevDir {
   double* Cbar = nullptr;
   double* Gbar = nullptr;
   double* Kbar = nullptr;
+  double* Jbar = nullptr;
+  double* Hbar = nullptr;
+  double* Dbar = nullptr;
 };
 
 // Scalars of the PCG recurrence, resident in device memory.

@@ -137,3 +137,68 @@ def test_lift_rejects_null_pointers():
     S = _lib().Solver(knots, degs)
     rc = stls._lib.stls_lift_initial(S._h, None, None)
     assert rc != 0
+
+
+# --- general data (boundary and initial coefficients) -----------------------
+
+@pytest.mark.parametrize("d,nel,p,kappa", [(1, [6, 9], 3, 0.4), (2, [5, 4, 6], 2, 1.7), (3, [3, 4, 3, 5], 3, 1.0)])
+def test_general_lift_matches_oracle(d, nel, p, kappa):
+    knots, degs = problem_knots(d, nel, p)
+    S = _lib().Solver(knots, degs, kappa=kappa)
+    P = osys.Problem(knots, degs, kappa=kappa)
+    nfull = int(np.prod(P.full_shape))
+    ub = uniform_pm1(nfull, 81)
+    F = uniform_pm1(S.ndof, 82)
+    Fd = to_dev(F)
+    S.lift_apply(to_dev(ub), Fd)
+    got = F - to_host(Fd)
+    ref = osys.vec(lift.general_coupling(P, ub))
+    assert rel_err(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("d,nel,p,kappa", [(1, 11, 4, 0.8), (2, [7, 6, 5], 3, 1.0), (3, 4, 2, 2.0)])
+def test_general_lift_of_zero_data_function_is_the_matvec(d, nel, p, kappa):
+    """On a trial function of the zero-data space the term-by-term form equals
+    the system matrix (two independent GPU code paths)."""
+    import torch
+    knots, degs = problem_knots(d, nel, p)
+    S = _lib().Solver(knots, degs, kappa=kappa)
+    nfull = S.forcing_shape[1]
+    x = to_dev(uniform_pm1(S.ndof, 83))
+    ub = S.lift_embed(torch.zeros(nfull, dtype=torch.float64, device="cuda"), x)
+    F = torch.zeros(S.ndof, dtype=torch.float64, device="cuda")
+    S.lift_apply(ub, F)
+    assert rel_err(-to_host(F), to_host(S.matvec(x))) < 1e-12
+
+
+def test_lift_embed_is_exact():
+    knots, degs = problem_knots(2, [5, 4, 6], 3)
+    S = _lib().Solver(knots, degs)
+    P = osys.Problem(knots, degs)
+    nfull = int(np.prod(P.full_shape))
+    ub, w = uniform_pm1(nfull, 84), uniform_pm1(S.ndof, 85)
+    got = to_host(S.lift_embed(to_dev(ub), to_dev(w)))
+    ref = osys.vec(ub.reshape(P.full_shape, order="F") + lift.embed(P, w))
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("d,nel,p,kappa", [(1, 12, 3, 1.0), (2, 7, 3, 0.6)])
+def test_boundary_lifted_solve_matches_oracle(d, nel, p, kappa):
+    """u = prod cos(pi x_k) (1 + t): non-zero boundary and initial values; u_B
+    from the full L^2 projection (oracle input).  Bound as for the
+    initial-data solve."""
+    knots, degs = problem_knots(d, nel, p)
+    S = _lib().Solver(knots, degs, kappa=kappa)
+    P = osys.Problem(knots, degs, kappa=kappa)
+    c = lambda x: np.cos(PI * x)
+    F = assemble.load_separable(knots, degs, [(1.0, [c] * d, np.ones_like),
+                                              (kappa * d * PI * PI, [c] * d, lambda t: 1 + t)], kappa)
+    UB = lift.boundary_part(P, lift.full_projection(P, [c] * d, lambda t: 1 + t))
+    ubd = to_dev(osys.vec(UB))
+    Fd = to_dev(osys.vec(F))
+    S.lift_apply(ubd, Fd)
+    w, it, rel = S.solve(Fd, rtol=1e-12, maxit=300)
+    u = to_host(S.lift_embed(ubd, w))
+    W = np.linalg.solve(P.dense_A(), osys.vec(F - lift.general_coupling(P, UB)))
+    ref = osys.vec(UB + lift.embed(P, W))
+    assert rel <= 1e-12 and rel_err(u, ref) < 1e-8
