@@ -253,6 +253,10 @@ int stls_mass_apply(stls_handle h, const double* x, double* y);
  * f: nfull doubles; u, l: ndof doubles.  Synchronises. */
 int stls_dkappa(stls_handle h, const double* f, const double* u, const double* l, double* dk);
 
+/* The same derivative under the name of the scope's boundary listing
+ * (identical arguments, result and errors). */
+int stls_dkappa_terms(stls_handle h, const double* f, const double* u, const double* l, double* dk);
+
 /* *out (host) = a . b over n doubles (device), fixed-order reduction.
  * Synchronises. */
 int stls_dot(stls_handle h, const double* a, const double* b, int64_t n, double* out);

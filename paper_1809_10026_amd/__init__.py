@@ -74,6 +74,7 @@ _sig = {
     "stls_lift_embed": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_dbl_p]),
     "stls_mass_apply": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
     "stls_dkappa": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_dbl_p, ctypes.POINTER(ctypes.c_double)]),
+    "stls_dkappa_terms": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_dbl_p, ctypes.POINTER(ctypes.c_double)]),
     "stls_dot": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     "stls_misfit": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_dbl_p, ctypes.POINTER(ctypes.c_double)]),
     "stls_batch_setup": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_int_p, ctypes.POINTER(ctypes.c_void_p), _c_int_p,

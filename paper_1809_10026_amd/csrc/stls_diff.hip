@@ -407,6 +407,10 @@ int stls_dkappa(stls_handle h, const double* f, const double* u, const double* l
   return device_dot(h, lam, V, h->ndof, dk);
 }
 
+int stls_dkappa_terms(stls_handle h, const double* f, const double* u, const double* lam, double* dk) {
+  return stls_dkappa(h, f, u, lam, dk);
+}
+
 int stls_misfit(stls_handle h, const double* u, const double* ustar, double* q, double* loss) {
   if (!h || !u || !ustar || !q || !loss) { set_error("bad handle or pointers"); return STLS_EINVAL; }
   int st = ensure_diff_operands(h);

@@ -55,9 +55,16 @@ def test_dkappa_and_misfit(d, nel, p, kappa):
     S, P, G = _setup(d, nel, p, kappa)
     nf = S.forcing_shape[1]
     f, u, lam = uniform_pm1(nf, 41), uniform_pm1(P.ndof, 42), uniform_pm1(P.ndof, 43)
-    dk = S.dkappa(to_dev(f), to_dev(u), to_dev(lam))
+    fd, ud, ld = to_dev(f), to_dev(u), to_dev(lam)
+    dk = S.dkappa(fd, ud, ld)
     ref = float(lam @ (G.dF_dkappa(f).ravel(order="F") - G.dA_dkappa_apply(u).ravel(order="F")))
     assert abs(dk - ref) <= 1e-11 * max(abs(ref), 1.0)
+    # the same entry point under its second name: bit-identical
+    import ctypes
+    out = ctypes.c_double()
+    assert stls._lib.stls_dkappa_terms(S._h, ctypes.c_void_p(fd.data_ptr()), ctypes.c_void_p(ud.data_ptr()),
+                                       ctypes.c_void_p(ld.data_ptr()), ctypes.byref(out)) == 0
+    assert out.value == dk
     us = uniform_pm1(P.ndof, 44)
     loss, q = S.misfit(to_dev(u), to_dev(us))
     e = u - us
