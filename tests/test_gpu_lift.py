@@ -36,7 +36,9 @@ def _lib():
 
 
 @pytest.mark.parametrize("d,nel,p,kappa", [(1, [7, 9], 2, 1.0), (1, [12, 5], 5, 0.3), (2, [5, 6, 7], 3, 2.5),
-                                           (2, [9, 4, 3], 4, 1.0), (3, [3, 4, 5, 4], 2, 0.8), (3, 4, 3, 1.0)])
+                                           (2, [9, 4, 3], 4, 1.0), (3, [3, 4, 5, 4], 2, 0.8), (3, 4, 3, 1.0),
+                                           # linear time splines (one coupled row); a single time element
+                                           (2, [5, 6, 7], [3, 3, 1], 1.4), (1, [8, 1], [4, 2], 0.9)])
 def test_lift_coupling_matches_oracle(d, nel, p, kappa):
     knots, degs = problem_knots(d, nel, p)
     S = _lib().Solver(knots, degs, kappa=kappa)
@@ -141,7 +143,8 @@ def test_lift_rejects_null_pointers():
 
 # --- general data (boundary and initial coefficients) -----------------------
 
-@pytest.mark.parametrize("d,nel,p,kappa", [(1, [6, 9], 3, 0.4), (2, [5, 4, 6], 2, 1.7), (3, [3, 4, 3, 5], 3, 1.0)])
+@pytest.mark.parametrize("d,nel,p,kappa", [(1, [6, 9], 3, 0.4), (2, [5, 4, 6], 2, 1.7), (3, [3, 4, 3, 5], 3, 1.0),
+                                           (2, [5, 6, 7], [3, 3, 1], 1.4), (1, [8, 1], [4, 2], 0.9)])
 def test_general_lift_matches_oracle(d, nel, p, kappa):
     knots, degs = problem_knots(d, nel, p)
     S = _lib().Solver(knots, degs, kappa=kappa)
