@@ -358,9 +358,8 @@ def gpu_lifting(stls, torch, knots, degs, reps=20):
             "coupling_s": dt, "combine_s": dc, "algorithmic_bytes": nbytes,
             "coupling_GB_per_s": nbytes / dt / 1e9, "kronecker_terms": 1 + d + d * (d - 1) // 2,
             "launches": (1 + d + d * (d - 1) // 2) * (d + 1),
-            "general": {"apply_s": dg, "embed_s": de, "kronecker_terms": gterms, "launches": gterms * (d + 1),
-                        "algorithmic_bytes": 8 * nfull + 16 * S.ndof,
-                        "pass_bytes": gterms * (d + 1) * 16 * nfull}}
+            "general": {"apply_s": dg, "embed_s": de, "kronecker_terms": gterms,
+                        "algorithmic_bytes": 8 * nfull + 16 * S.ndof}}
 
 
 def cpu_lifting(knots, degs):

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <vector>
 
 #include "stls_internal.h"
@@ -120,6 +121,22 @@ int apply_chain(stls_ctx* h, const double* src, double* dst, const std::vector<F
     cur[k] = fac[k].n_out;
     in = out;
   }
+  return STLS_OK;
+}
+
+// One mode product on a tensor of mode sizes cur[0..nm-1]: out (+)= coef F in.
+int apply_mode(stls_ctx* h, const double* in, double* out, const std::vector<int>& cur, int k, const Fac& f,
+               double coef, bool accumulate) {
+  long long L = 1, R = 1;
+  for (int m = 0; m < k; ++m) L *= cur[m];
+  for (int m = k + 1; m < (int)cur.size(); ++m) R *= cur[m];
+  const long long total = L * f.n_out * R;
+  prof_begin(h);
+  hipLaunchKernelGGL(band_rect_kernel, dim3(grid_for(total)), dim3(kT), 0, h->stream, in, out, (int)L, f.n_in, f.n_out,
+                     (int)R, f.band, f.p, f.off, f.trans, coef, accumulate ? 1 : 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "band_rect_kernel launch");
+  prof_end(h, PROF_DIFF);
   return STLS_OK;
 }
 
@@ -314,12 +331,78 @@ int stls_lift_combine(stls_handle h, const double* u0, const double* x, double* 
   return e == hipSuccess ? STLS_OK : hip_fail(e, "hipMemcpyAsync");
 }
 
+// F -= sum over terms of c (F_t (x) F_{d-1} (x) ... (x) F_0) u_B, evaluated as
+// a depth-first walk over the terms' spatial factors: modes 0 .. d-2 reuse
+// the intermediate of every distinct prefix, the last spatial mode adds
+// c times its result into one full-time sum per time factor, and each sum
+// takes one time product into F.  (16 chains of 4 products at d = 3 become
+// 33 products.)
 int stls_lift_apply(stls_handle h, const double* ub, double* F) {
   if (!h || !ub || !F) { set_error("bad handle or pointers"); return STLS_EINVAL; }
   int st = ensure_diff_operands(h);
   if (st) return st;
-  for (auto& t : general_lift_terms(h))
-    if ((st = apply_chain(h, ub, F, t.second, -t.first, true, h->ftmp[0], h->ftmp[1]))) return st;
+  const int d = h->d;
+  for (int g = 0; g < 4 && !st; ++g)
+    if (!h->lgrp[g] && hipMalloc((void**)&h->lgrp[g], sizeof(double) * (size_t)h->nfull) != hipSuccess) {
+      set_error("hipMalloc lifting workspace");
+      st = STLS_ENOMEM;
+    }
+  if (st) return st;
+  const auto terms = general_lift_terms(h);
+  std::vector<const double*> tband;  // distinct time factors, in order of first use
+  std::vector<int> tgroup(terms.size());
+  for (size_t i = 0; i < terms.size(); ++i) {
+    const double* b = terms[i].second[d].band;
+    size_t g = 0;
+    while (g < tband.size() && tband[g] != b) ++g;
+    if (g == tband.size()) tband.push_back(b);
+    tgroup[i] = (int)g;
+  }
+  if (tband.size() > 4) { set_error("lifting: unexpected number of time factors"); return STLS_EINVAL; }
+  std::vector<bool> started(tband.size(), false);
+  std::vector<int> cur0(d + 1);
+  for (int k = 0; k <= d; ++k) cur0[k] = h->dd[k].m;
+  // walk(level k, input tensor, its mode sizes, the terms that share the prefix)
+  std::function<int(int, const double*, std::vector<int>, const std::vector<int>&)> walk =
+      [&](int k, const double* in, std::vector<int> cur, const std::vector<int>& sub) -> int {
+    std::vector<const double*> seen;
+    for (int i : sub) {
+      const Fac& f = terms[i].second[k];
+      bool dup = false;
+      for (const double* b : seen) dup = dup || b == f.band;
+      if (dup) continue;
+      seen.push_back(f.band);
+      std::vector<int> next;
+      for (int j : sub)
+        if (terms[j].second[k].band == f.band) next.push_back(j);
+      std::vector<int> out = cur;
+      out[k] = f.n_out;
+      int s2;
+      if (k < d - 1) {
+        double* tmp = h->ftmp[k % 2];
+        if ((s2 = apply_mode(h, in, tmp, cur, k, f, 1.0, false))) return s2;
+        if ((s2 = walk(k + 1, tmp, out, next))) return s2;
+      } else {
+        for (int j : next) {
+          const int g = tgroup[j];
+          if ((s2 = apply_mode(h, in, h->lgrp[g], cur, k, f, terms[j].first, started[g]))) return s2;
+          started[g] = true;
+        }
+      }
+    }
+    return STLS_OK;
+  };
+  std::vector<int> all(terms.size());
+  for (size_t i = 0; i < terms.size(); ++i) all[i] = (int)i;
+  if ((st = walk(0, ub, cur0, all))) return st;
+  std::vector<int> curt(d + 1);
+  for (int k = 0; k < d; ++k) curt[k] = h->dd[k].n;
+  curt[d] = h->dd[d].m;
+  for (size_t g = 0; g < tband.size(); ++g) {
+    if (!started[g]) continue;
+    const Fac ft = terms[std::find(tgroup.begin(), tgroup.end(), (int)g) - tgroup.begin()].second[d];
+    if ((st = apply_mode(h, h->lgrp[g], F, curt, d, ft, -1.0, true))) return st;
+  }
   return STLS_OK;
 }
 

@@ -129,6 +129,7 @@ struct stls_ctx {
   double* partials = nullptr;
   double* dres = nullptr;          // device scalar result of stls_dot
   double* ftmp[2] = {nullptr, nullptr};  // full-space temporaries (differentiation ops)
+  double* lgrp[4] = {nullptr, nullptr, nullptr, nullptr};  // lifting: one full-space sum per time factor
   int64_t nfull = 0;               // prod of full sizes m_k
   bool diff_ready = false;
   stls::PcgScalars* scal = nullptr;
