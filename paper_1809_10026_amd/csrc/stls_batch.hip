@@ -34,6 +34,7 @@ constexpr int kBNM = 7;               // max 16-row tiles per direction (n <= 11
 constexpr int kVecChunk = 4096;       // elements per vector work item
 constexpr int kInSteps = 8;           // column steps per inner-stage work item
 constexpr int kOLb = 16, kOMaxTd = 16, kOSlots = 2;
+constexpr int kOChunk = 32;            // outer stage: time slices per work item (at most)
 
 typedef double d4b_t __attribute__((ext_vector_type(4)));
 
@@ -852,8 +853,8 @@ int stls_batch_setup(int nprob, int d, const int* nknots, const double* const* k
     P.ntd = (nd + kOMaxTd - 1) / kOMaxTd;
     P.Td = (nd + P.ntd - 1) / P.ntd;
     P.nlb = (L + kOLb - 1) / kOLb;
-    P.nchunk = 1;
-    P.Tc = nt;
+    P.nchunk = (nt + kOChunk - 1) / kOChunk;  // time chunks (each re-reads 2p halo slices)
+    P.Tc = (nt + P.nchunk - 1) / P.nchunk;
     cnt_outer[i] = P.nlb * P.ntd * P.nchunk;
     cnt_vec[i] = (P.N + kVecChunk - 1) / kVecChunk;
     {
