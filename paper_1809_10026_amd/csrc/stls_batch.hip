@@ -199,10 +199,16 @@ __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, d
       __syncthreads();
       gemm(B.Ab[mode]);
     }
+    // outputs through range-checked buffer accesses (padding rows, columns
+    // past the problem and the clamped tile are out of range): a row tile's
+    // dot operand loads are all issued before the first is used
+    const size_t bytes = sizeof(double) * (size_t)B.N;
+    const __amdgpu_buffer_rsrc_t rY = buf_rsrc(Yp, bytes);
+    const __amdgpu_buffer_rsrc_t rD = buf_rsrc(DOT ? dotv + B.off : Yp, bytes);
     double ds = 0.0;
 #pragma unroll
-    for (int t = 0; t < kH; ++t) {
-      if (wr * kH + t >= NMT) continue;
+    for (int t = 0; t < kH; ++t) {  // one row tile at a time: 8 dot operands live
+      int off[2][4];
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
@@ -210,11 +216,22 @@ __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, d
           int i, cc;
           if (TRANS) { cc = c0 + wq * 32 + 16 * q + (lane >> 4) + 4 * r; i = (wr * kH + t) * 16 + (lane & 15); }
           else { cc = c0 + col0 + 16 * q; i = (wr * kH + t) * 16 + (lane >> 4) + 4 * r; }
-          if (cc < ncols && i < n) {
-            const size_t o = (size_t)base(cc) + (size_t)i * L;
-            Yp[o] = acc[t][q][r];
-            if (DOT) ds += acc[t][q][r] * dotv[B.off + o];
-          }
+          const bool ok = wr * kH + t < NMT && cc < ncols && i < n;
+          off[q][r] = ok ? (int)sizeof(double) * (base(cc) + i * L) : kOutOfRange;
+        }
+      double dv[2][4];
+      if (DOT) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) dv[q][r] = buf_load_f64(rD, off[q][r]);
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          buf_store(acc[t][q][r], rY, off[q][r]);
+          if (DOT) ds += acc[t][q][r] * dv[q][r];  // 0 where out of range
         }
     }
     if (DOT) {
