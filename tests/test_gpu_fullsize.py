@@ -2,8 +2,10 @@
 the benchmark times: d = 3, p = 4, 48 elements per direction, N = 6,375,000,
 right-hand side U[-1, 1] with the benchmark's seed.
 
-The oracle applies the matvec and the FD preconditioner to the whole vector
-in a few seconds, so those are compared entry by entry; a full oracle PCG
+The oracle applies the matvec, the FD preconditioner and the initial-data
+lifting to the whole vector in a few seconds, so those are compared entry by
+entry; the general lifting is checked by its identity with the matvec on
+zero-data functions; a full oracle PCG
 would take about a minute, so the solves are checked by properties that hold
 at any size: the oracle's matvec gives the true residual of the GPU solution,
 and the solutions of the different FD precisions agree to the solve
@@ -147,3 +149,29 @@ def test_fullsize_d2_workload_against_oracle(rhs):
     print(f"d2 {rhs}: {it} iterations (oracle {info['iters']}), true relres {true_rel:.2e}", flush=True)
     assert abs(it - info["iters"]) <= 1 and rel <= c["rtol"] and true_rel < 2 * c["rtol"]
     assert rel_err(xo, x_ref) < 2 * 2 * 10 * c["rtol"]
+
+
+def test_fullsize_lift_initial(full):
+    """Lifting of initial data at the benchmark shape: the whole coupling
+    against the oracle's term-by-term expansion (it takes the oracle well
+    under a second); bound as in the small-size lifting tests."""
+    from oracle import lift
+    S, P, _ = full
+    u0 = uniform_pm1(S.ns, 91)
+    F = uniform_pm1(S.ndof, 92)
+    Fd = to_dev(F)
+    S.lift_initial(to_dev(u0), Fd)
+    assert rel_err(F - to_host(Fd), osys.vec(lift.initial_coupling(P, u0))) < 1e-12
+
+
+def test_fullsize_general_lift_of_zero_data_function_is_the_matvec(full):
+    """General lifting at the benchmark shape (52^4 full space), by the
+    property that holds at any size: on an embedded zero-data vector the
+    term-by-term form equals the system matrix (independent GPU paths)."""
+    import torch
+    S, _, _ = full
+    x = to_dev(uniform_pm1(S.ndof, 93))
+    ub = S.lift_embed(torch.zeros(S.forcing_shape[1], dtype=torch.float64, device="cuda"), x)
+    F = torch.zeros(S.ndof, dtype=torch.float64, device="cuda")
+    S.lift_apply(ub, F)
+    assert rel_err(-to_host(F), to_host(S.matvec(x))) < 1e-12
