@@ -201,3 +201,26 @@ def test_graph_replay_matches_direct_launches(full):
         assert np.isfinite(to_host(y)).all()
     print(f"{len(probs)} problems, {max(its0)} iterations: direct {t_direct * 1e3:.1f} ms, graph {t_graph * 1e3:.1f} ms",
           flush=True)
+
+
+def test_degree_six_batch_matches_single_problems():
+    """d = 2 batch with the largest supported degree (p = 6) next to p = 2:
+    the p = 6 instances of the inner and outer matvec stages and of the FD
+    kernels against the standalone operators and solves."""
+    specs = [((9, 8, 10), 6, 0.8), ((7, 12, 5), 2, 1.9), ((5, 6, 4), 6, 3.0)]
+    B, probs = _batch(specs)
+    off = B.offsets
+    x = to_dev(uniform_pm1(B.total, 66))
+    y = B.matvec(x)
+    s = B.prec_apply(x)
+    b = to_dev(uniform_pm1(B.total, 67))
+    xb, its, rels = B.solve(b, rtol=1e-8, maxit=300)
+    assert all(r <= 1e-8 for r in rels)
+    for i in range(len(probs)):
+        S = _single(B, i, probs)
+        xi = x[off[i]:off[i + 1]].contiguous()
+        assert rel_err(to_host(y[off[i]:off[i + 1]]), to_host(S.matvec(xi))) < 1e-13
+        assert rel_err(to_host(s[off[i]:off[i + 1]]), to_host(S.prec_apply(xi))) < 1e-12
+        xs, it_s, _ = S.solve(b[off[i]:off[i + 1]].contiguous(), rtol=1e-8)
+        assert abs(its[i] - it_s) <= 1
+        assert rel_err(to_host(xb[off[i]:off[i + 1]]), to_host(xs)) < 1e-7
