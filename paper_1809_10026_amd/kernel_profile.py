@@ -10,6 +10,13 @@ kernel rather than a DMA-engine copy); its FETCH_SIZE and WRITE_SIZE readings
 give the factors that turn the counters into HBM bytes.  Then the d = 3,
 p = 4, 48-element workload (ndof 6,375,000) is solved with the BF16x3 FD
 preconditioner (the benchmark's headline mode) ``--solves`` times.
+
+With ``--batch`` the workload is instead the batched solve of 256 uneven
+d = 2 problems (n_el per direction uniform on 16..96, p uniform on {2..5},
+kappa log-uniform on [0.1, 10], right-hand sides U[-1, 1] with seeds
+20180927 + i, rtol 1e-8, FP64 FD), solved ``--solves`` times:
+
+    rocprofv3 --kernel-trace --stats -d OUT -o run -- python3 -m paper_1809_10026_amd.kernel_profile --batch
 """
 from __future__ import annotations
 
@@ -26,11 +33,15 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--solves", type=int, default=2)
     ap.add_argument("--mode", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--batch", action="store_true", help="the 256-problem batched solve instead")
     args = ap.parse_args()
     import torch
 
     import paper_1809_10026_amd as stls
     from stls_inputs import CONFIGS, problem_knots, uniform_pm1
+
+    if args.batch:
+        return batch(stls, torch, args.solves)
 
     src = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
@@ -49,6 +60,21 @@ def main():
         _, it, rel = S.solve(b, cfg["rtol"], 200, out=x)
         torch.cuda.synchronize()
         print(f"[kernel_profile] solve {i}: {it} iterations, relres {rel:.2e}", flush=True)
+
+
+def batch(stls, torch, solves):
+    import numpy as np
+
+    from stls_inputs import batch_params, batch_problem_knots, uniform_pm1
+    nel, p, kappa = batch_params()
+    B = stls.Batch([(*batch_problem_knots(nel[i], p[i]), float(kappa[i])) for i in range(len(p))])
+    off = B.offsets
+    b = torch.as_tensor(np.concatenate([uniform_pm1(off[i + 1] - off[i], 20180927 + i)
+                                        for i in range(len(p))])).cuda()
+    for i in range(solves):
+        _, its, rels = B.solve(b, 1e-8, 500)
+        torch.cuda.synchronize()
+        print(f"[kernel_profile] batch solve {i}: {max(its)} iterations, max relres {max(rels):.2e}", flush=True)
 
 
 if __name__ == "__main__":
