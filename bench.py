@@ -7,11 +7,13 @@ updates and dot products), on the 3-D-space workload: unit cube x (0,1),
 p = 4 (C^3) splines, 48 elements per direction, ndof = 50^3 * 51 = 6,375,000,
 right-hand side i.i.d. uniform[-1,1] (seed 10026), inputs resident in HBM.
 
-The headline value is the mixed-precision solve (FD n-mode products in FP32
-on MFMA inside the FP64 PCG); the FP64-plain solve, per-precision FD
-application rates, the matvec rate, errors, a roofline of the dominant kernel
-(HIP-event durations measured in the timed region) and the oracle timed on the
-host are printed in the same JSON line.
+The headline value is the faster of the two mixed-precision solves (FD
+n-mode products in FP32, or in BF16x3 split products, on MFMA inside the FP64
+PCG); the FP64-plain solve, per-precision FD application rates and MFMA
+fractions, the matvec rate, errors against the FP64 oracle's own solution,
+the roofline of the dominant kernel (HIP-event durations measured on the
+solver's stream) and the oracle timed on the host cores are printed in the
+same JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -34,36 +36,119 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(cls, mode, five_pass, N):
-    """Algorithmic HBM bytes per launch of a profiling class (each stream read
-    or written once, FP64 PCG vectors, FP32 FD intermediates unless FP64)."""
-    if cls == "fd_slab":  # slab forward r -> FP32 (12 B/dof), backward FP32 -> s plus the dot with r (20 B/dof)
-        return 16.0 * N
-    if cls == "fd_space":
-        if five_pass:  # FP32 -> FP32 single-mode passes
-            return 8.0 * N
-        sb = 8.0 if mode == "fp64" else 4.0  # six passes: first reads r, last writes s and reads r for the dot
-        return (24.0 + 10.0 * sb) / 6.0 * N
-    if cls == "fd_time":
-        return 8.0 * N if five_pass else (16.0 if mode == "fp64" else 8.0) * N
-    return {"mv_inner2": 32.0 * N,   # x in, A, B, C out
-            "mv_outer": 40.0 * N,    # A, B, C and the dot operand in, y out
-            "vec": 36.0 * N}.get(cls)  # mean of x,r update (48 B/dof) and p update (24 B/dof)
+# Algorithmic work per unknown (DOF) of each step of one PCG iteration
+# (the minimum any implementation must move or compute):
+#   FD apply   read r, write s (FP64): 16 B; 4 (d n_s + n_t) flops (§4.5)
+#   matvec     read x, write y (FP64): 16 B
+STEP_BYTES_PER_DOF = {"fd": 16.0, "matvec": 16.0}
+# The kernels of each step (profiling classes of the library).
+STEPS = {"matvec": ("mv_inner1", "mv_inner2", "mv_outer"),
+         "fd": ("fd_slab_fwd", "fd_slab_bwd", "fd_space", "fd_time")}
+# Bytes each kernel of the implementation moves per DOF (every stream read or
+# written once).  FD: five passes (FP32 intermediates in the mixed modes,
+# FP64 in the FP64 mode).
+def impl_bytes(cls, mode):
+    w = 8.0 if mode == "fp64" else 4.0
+    return {"fd_slab_fwd": 8.0 + w,         # r in, intermediate out
+            "fd_slab_bwd": w + 16.0,        # intermediate in, s out, r in for r . s
+            "fd_space": 2 * w, "fd_time": 2 * w,
+            "mv_inner2": 32.0,              # x in, A, B, C out
+            "mv_inner1": 32.0,
+            "mv_outer": 40.0,               # A, B, C and the dot operand in, y out
+            "vec_xr": 48.0,                 # x, r, p, q in; x, r out
+            "vec_p": 24.0}.get(cls)         # z, p in; p out
 
 
-def measured_traffic(cls):
-    """HBM bytes per launch of ``cls`` from the committed counter summary, if
-    it was taken on the current kernel sources; else None."""
+def measured_traffic(classes):
+    """HBM bytes per launch summed over ``classes`` from the committed counter
+    summary, if it was taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     from paper_1809_10026_amd.profile_summary import source_hash
     with open(path) as f:
         data = json.load(f)
-    if data.get("source_sha256") != source_hash() or cls not in data.get("classes", {}):
+    if data.get("source_sha256") != source_hash():
         return None
-    c = data["classes"][cls]
-    return c["fetch_bytes"] + c["write_bytes"]
+    tot = 0.0
+    for cls in classes:
+        c = data.get("classes", {}).get(cls)
+        if c is None:
+            return None
+        tot += c["fetch_bytes"] + c["write_bytes"]
+    return tot
+
+
+def kernel_table(prof, mode, N):
+    """Per-class launches, durations and HBM rates (implementation bytes)."""
+    five_pass = prof.get("fd_slab_fwd", (0, 0.0))[0] > 0
+    out = []
+    for cls, (launches, ms) in prof.items():
+        if launches == 0:
+            continue
+        avg_s = ms / launches / 1e3
+        e = dict(kernel=cls, launches=launches, total_ms=round(ms, 4), avg_us=round(avg_s * 1e6, 3))
+        ib = impl_bytes(cls, mode)
+        if ib is not None and (five_pass or not cls.startswith("fd_")):
+            e.update(bytes_per_launch=ib * N, GBs=round(ib * N / avg_s / 1e9, 1),
+                     hbm_frac=round(ib * N / avg_s / 1e9 / PEAK["hbm_GBs"], 4))
+        out.append(e)
+    out.sort(key=lambda e: -e["total_ms"])
+    return out
+
+
+def dominant_roofline(table, prof, mode, N):
+    """Roofline of the kernel with the largest total time in the headline
+    solve.  A kernel that is one stage of a multi-kernel step (the matvec's
+    two stages, the FD's passes) is priced as that step: the step's
+    algorithmic bytes over the summed average durations of its kernels per
+    application."""
+    dom = table[0]["kernel"]
+    step = next((st for st, cl in STEPS.items() if dom in cl), None)
+    if step is None:
+        e = table[0]
+        ib = impl_bytes(dom, mode)
+        avg_s = e["avg_us"] * 1e-6
+        tr = measured_traffic([dom])
+        return dict(kernel=dom, bound="hbm", achieved=round(ib * N / avg_s / 1e9, 3), peak=PEAK["hbm_GBs"],
+                    unit="GB/s", frac=round(ib * N / avg_s / 1e9 / PEAK["hbm_GBs"], 4),
+                    traffic=None if tr is None else round(tr / 1e6, 3), traffic_unit="MB per launch",
+                    avg_us=e["avg_us"])
+    members = [c for c in STEPS[step] if prof.get(c, (0, 0.0))[0] > 0]
+    # launches of the step = launches of its first-stage kernel; durations per application
+    napp = max(prof[c][0] for c in members)
+    per_app = {c: prof[c][1] / 1e3 / napp for c in members}
+    t = sum(per_app.values())
+    alg = STEP_BYTES_PER_DOF[step] * N
+    impl = sum((impl_bytes(c, mode) or 0.0) * prof[c][0] / napp for c in members) * N
+    tr = measured_traffic_per_app(members, prof, napp)
+    return dict(kernel=f"{step}: " + " + ".join(members) + f" (dominant: {dom})", bound="hbm",
+                achieved=round(alg / t / 1e9, 3), peak=PEAK["hbm_GBs"], unit="GB/s",
+                frac=round(alg / t / 1e9 / PEAK["hbm_GBs"], 4),
+                traffic=None if tr is None else round(tr / 1e6, 3), traffic_unit="MB per application",
+                algorithmic_MB_per_launch=round(alg / 1e6, 3), avg_us=round(t * 1e6, 3),
+                impl_MB_per_launch=round(impl / 1e6, 3), impl_achieved=round(impl / t / 1e9, 3),
+                impl_frac=round(impl / t / 1e9 / PEAK["hbm_GBs"], 4),
+                stage_us={c: round(v * 1e6, 3) for c, v in per_app.items()})
+
+
+def measured_traffic_per_app(members, prof, napp):
+    """Counter traffic of one application of a multi-kernel step."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    from paper_1809_10026_amd.profile_summary import source_hash
+    with open(path) as f:
+        data = json.load(f)
+    if data.get("source_sha256") != source_hash():
+        return None
+    tot = 0.0
+    for c in members:
+        e = data["classes"].get(c)
+        if e is None:
+            return None
+        tot += (e["fetch_bytes"] + e["write_bytes"]) * prof[c][0] / napp
+    return tot
 
 
 def main():
@@ -143,10 +228,13 @@ def main():
         log(f"{name}: solve {dt*1e3:.3f} ms, {it} its, relres {rel:.2e}, true {res[name]['true_relres']:.2e}")
     mixed = min(("fp32", "bf16x3"), key=lambda m: res[m]["time_s"])
     log(f"headline mixed mode: {mixed}")
-    # the same steps again with HIP events around every launch: per-kernel durations
-    dt_prof, _, _, prof = timed_solves(modes[mixed], args.steps, 0, profile=True)
-    res[mixed]["prof"] = prof
-    log(f"profiled repetition: {dt_prof*1e3:.3f} ms/step")
+    # the same steps again with HIP events around every launch on the solver's
+    # stream: per-kernel durations (every mode)
+    for name, mode in modes.items():
+        dt_prof, _, _, prof = timed_solves(mode, args.steps, 0, profile=True)
+        res[name]["prof"] = prof
+        res[name]["prof_step_s"] = dt_prof
+        log(f"{name}: profiled repetition {dt_prof*1e3:.3f} ms/step")
     for name, mode in modes.items():
         res[name]["fd_apply_s"] = fd_rate(mode)
         log(f"{name}: FD apply {res[name]['fd_apply_s']*1e6:.1f} us")
@@ -172,37 +260,33 @@ def main():
         log(f"{name} scaled: solve {dt*1e3:.3f} ms, {it} its, true {scaled[name]['true_relres']:.2e}")
     S.set_fd_scaling(False)
 
-    # roofline of the dominant kernel class of the headline (timed) solves
-    prof = res[mixed]["prof"]
-    five_pass = prof.get("fd_slab", (0, 0.0))[0] > 0
-    classes = []
-    for cls, (launches, ms) in prof.items():
-        if launches == 0:
-            continue
-        avg_s = ms / launches / 1e3
-        entry = dict(kernel=cls, launches=launches, total_ms=ms, avg_us=avg_s * 1e6)
-        byts = kernel_bytes(cls, mixed, five_pass, N)
-        if byts is not None:
-            entry.update(bound="hbm", bytes_per_launch=byts, achieved=byts / avg_s / 1e9, peak=PEAK["hbm_GBs"],
-                         unit="GB/s")
-            entry["frac"] = entry["achieved"] / entry["peak"]
-        classes.append(entry)
-    classes.sort(key=lambda e: -e["total_ms"])
-    dom = next(e for e in classes if "achieved" in e)
-    traffic = measured_traffic(dom["kernel"])
-    roofline = dict(kernel=dom["kernel"], bound=dom["bound"], achieved=round(dom["achieved"], 3),
-                    peak=dom["peak"], unit=dom["unit"], frac=round(dom["frac"], 4),
-                    traffic=None if traffic is None else round(traffic / 1e6, 3),
-                    traffic_unit="MB per launch", algorithmic_MB_per_launch=round(dom["bytes_per_launch"] / 1e6, 3),
-                    avg_us=round(dom["avg_us"], 3))
+    kernels = {m: kernel_table(res[m]["prof"], m, N) for m in modes}
+    roofline = dominant_roofline(kernels[mixed], res[mixed]["prof"], mixed, N)
+    # FD n-mode products against the MFMA peak of their arithmetic: useful
+    # flops 4 (d n_s + n_t) N per application (§4.5), x3 for the three bf16
+    # products of the split form
+    fd_flops = 4.0 * (sum(shape[:d]) + shape[d]) * N
+    fd_mfma = {}
+    for m, peak, mult in (("fp64", PEAK["fp64_TF"], 1), ("fp32", PEAK["fp32_TF"], 1), ("bf16x3", PEAK["bf16_TF"], 3)):
+        tf = mult * fd_flops / res[m]["fd_apply_s"] / 1e12
+        fd_mfma[m] = dict(useful_TFLOPs=round(tf, 3), peak_TFLOPs=peak, frac=round(tf / peak, 4),
+                          flops_per_apply=mult * fd_flops, apply_us=round(res[m]["fd_apply_s"] * 1e6, 2))
 
     err_norms = gpu_error_norms(stls, torch)
     batch = gpu_batch(stls, torch)
     lifting = gpu_lifting(stls, torch, knots, degs)
 
     cpu = None
+    err_vs_oracle = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(knots, degs, b.cpu().numpy(), res["fp64"]["iters"], N)
+        cpu, xo = cpu_baseline(knots, degs, b.cpu().numpy(), rtol, N)
+        import numpy as np
+        err_vs_oracle = {}
+        for m in modes:
+            xs = sol[m].cpu().numpy()
+            err_vs_oracle[m] = dict(rel_l2=float(np.linalg.norm(xs - xo) / np.linalg.norm(xo)),
+                                    max_abs=float(np.abs(xs - xo).max()), max_abs_oracle=float(np.abs(xo).max()))
+            log(f"{m}: error vs oracle solution {err_vs_oracle[m]['rel_l2']:.2e} (relative 2-norm)")
         err_norms["oracle_cpu"] = cpu_error_norms()
         lifting["oracle_cpu"] = cpu_lifting(knots, degs)
 
@@ -229,7 +313,9 @@ def main():
         "iters": {m: res[m]["iters"] for m in modes},
         "true_relres": {m: res[m]["true_relres"] for m in modes},
         "err_vs_fp64_solution": err_vs_fp64,
+        "err_vs_oracle": err_vs_oracle,
         "fd_prec_dof_per_s": {k: N / v["fd_apply_s"] for k, v in res.items()},
+        "fd_mfma": fd_mfma,
         "matvec_dof_per_s": N / mv_s,
         "diag_scaled_prec": scaled,
         "error_norms": err_norms,
@@ -238,8 +324,11 @@ def main():
         "setup_s": setup_s,
         "roofline": roofline,
         "roofline_note": "kernel durations from HIP events recorded around every launch on the solver's "
-                         "stream in a repetition of the timed steps (%.3f ms/step with events)" % (dt_prof * 1e3),
-        "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in e.items()} for e in classes],
+                         "stream in a repetition of the timed steps (%.3f ms/step with events); achieved = "
+                         "algorithmic bytes (16 B per unknown for the matvec and for the FD apply) / duration; "
+                         "impl_* = the bytes this implementation's kernels move" % (res[mixed]["prof_step_s"] * 1e3),
+        "kernels": kernels[mixed],
+        "kernels_fp64": kernels["fp64"],
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -400,39 +489,42 @@ def cpu_error_norms(nel=32):
             "grid_points_per_s": grid / dt}
 
 
-def cpu_baseline(knots, degs, b, iters_fp64, N, sample_its=3):
-    """The FP64 oracle's own FD-PCG on the host cores: a bounded sample of
-    ``sample_its`` iterations on the same inputs, scaled to a full solve with
-    the GPU FP64 iteration count (DOF/s)."""
+def cpu_baseline(knots, degs, b, rtol, N):
+    """The FP64 oracle's own FD-PCG on the host cores: a full solve to rtol
+    from x = 0 on every core the BLAS uses (setup included), then one
+    iteration's cost on a single thread (the paper's setting).  Returns the
+    baseline record and the oracle's solution."""
     import numpy as np
 
     from oracle import fd, pcg, system
-    threads = None
-    try:
-        import threadpoolctl
-        threads = max((i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()), default=None)
-    except Exception:
-        pass
-    log(f"cpu baseline: oracle PCG, {sample_its} iterations")
+    import threadpoolctl
+    threads = max((i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()), default=None)
+    log(f"cpu baseline: oracle PCG to {rtol:g} on {threads} threads")
     t0 = time.perf_counter()
     P = system.Problem(knots, degs)
     F = fd.FD(P)
     setup = time.perf_counter() - t0
     t0 = time.perf_counter()
-    P.matvec(b)
-    t_mv = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    pcg.pcg(lambda v: system.vec(P.matvec(v)), lambda v: system.vec(F.apply(v)), b, 1e-30, maxit=sample_its)
-    dt = time.perf_counter() - t0
-    # pcg() ends with one true-residual matvec, which is not part of an iteration
-    per_it = (dt - t_mv) / sample_its
-    t_solve = per_it * iters_fp64 + setup
-    log(f"cpu baseline: {per_it:.2f} s/iteration")
-    return {"value": N / t_solve, "unit": "DOF/s", "cores": threads or os.cpu_count(), "kind": "oracle",
-            "sample": f"{sample_its} PCG iterations of the numpy FP64 oracle on the same workload "
-                      f"({dt:.1f} s, minus one true-residual matvec of {t_mv:.1f} s), scaled to "
-                      f"{iters_fp64} iterations + setup",
-            "seconds_per_iteration": per_it}
+    xo, info = pcg.pcg(lambda v: system.vec(P.matvec(v)), lambda v: system.vec(F.apply(v)), b, rtol, maxit=200)
+    t_solve = time.perf_counter() - t0
+    log(f"cpu baseline: setup {setup:.2f} s, solve {t_solve:.2f} s, {info['iters']} iterations")
+    # one iteration's operator work (matvec + FD apply) on one thread
+    with threadpoolctl.threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        q = system.vec(P.matvec(b))
+        system.vec(F.apply(q))
+        t1 = time.perf_counter() - t0
+    log(f"cpu baseline: one matvec + FD apply on 1 thread {t1:.2f} s")
+    total = setup + t_solve
+    return ({"value": N / total, "unit": "DOF/s", "cores": threads or os.cpu_count(), "kind": "oracle",
+             "sample": f"one full solve of the numpy FP64 oracle (setup {setup:.1f} s + PCG {t_solve:.1f} s, "
+                       f"{info['iters']} iterations to rtol {rtol:g}, x0 = 0) on the same workload and right-hand side",
+             "seconds": total, "iters": int(info["iters"]), "seconds_per_iteration": t_solve / max(1, info["iters"]),
+             "one_thread": {"cores": 1, "seconds_matvec_plus_fd": t1,
+                            "dof_per_s_estimate": N / (setup + t1 * info["iters"]),
+                            "note": "one matvec + one FD apply on one BLAS thread, times the iteration count, "
+                                    "plus the all-core setup"}},
+            np.asarray(xo))
 
 
 if __name__ == "__main__":

@@ -2,8 +2,9 @@
 // Algorithm 1 steps 2-4) in five passes:
 //   1. slab pass, forward:  modes 1 and 2 of every (i3, t) slab, r (FP64) -> FP32
 //   2. strided pass:        mode 3 forward
-//   3. strided fused pass:  time mode forward, division by the eigenvalue sum
-//                           (FP64 sum, FP32 quotient), time mode backward
+//   3. strided fused pass:  time mode forward, FP64 division by the FP64
+//                           eigenvalue sum (quotient rounded to FP32), time
+//                           mode backward
 //   4. strided pass:        mode 3 backward
 //   5. slab pass, backward: modes 2 and 1, FP32 -> s (FP64), partial sums of s . r
 // Every product W X is formed as W_hi X_hi + W_hi X_lo + W_lo X_hi on MFMA
@@ -230,7 +231,8 @@ __global__ __launch_bounds__(256) void fd_slab_bf16_kernel(const TI* __restrict_
 // straight from global memory (8 consecutive k of one column per lane), two
 // such units prefetched into registers (two register sets, unrolled, so that
 // no copy of an in-flight value forces an early wait).  FUSED: time mode,
-//   Q(i, c) = (W X)(i, c) / (lambda_t[i] + lambda_s[c])  (FP32 quotient),
+//   Q(i, c) = (W X)(i, c) / (lambda_t[i] + lambda_s[c])  (FP64 division,
+//             quotient rounded to FP32),
 //   Y = W2 Q,
 // with Q re-fragmented through a per-wave LDS scratch tile.  WL: the
 // forward operator's fragments are read from LDS at each product instead of
@@ -354,10 +356,10 @@ __global__ __launch_bounds__(kStridedWaves * 64, (WL && !FUSED) ? 4 : 2) void fd
           f4v q;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            // the quotient is rounded to FP32 at once: an FP32 reciprocal of
-            // the FP64 eigenvalue sum loses nothing the bf16x3 products keep
+            // eigenvalue sum and division in FP64, the quotient rounded
+            // once to FP32 (the precision of the pass's output)
             const int i = 16 * t + 4 * g + r;
-            const float qv = acc[t][r] * __builtin_amdgcn_rcpf((float)(lt_lds[i] + pls[d]));
+            const float qv = (float)((double)acc[t][r] / (lt_lds[i] + pls[d]));
             q[r] = i < n ? qv : 0.f;
           }
           *reinterpret_cast<f4v*>(myscr + cl * LDS_S + 16 * t + 4 * g) = q;
@@ -421,7 +423,7 @@ int launch_slab(stls_ctx* h, const TI* X, TO* Z, bool fwd, const double* dotv, d
                      n1, n2, nslab, W1h, W1l, W2h, W2l, dotv, partials, h->gate, diag_scale_args(h));
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "fd_slab_bf16_kernel launch");
-  prof_end(h, PROF_FD_SLAB);
+  prof_end(h, fwd ? PROF_FD_SLAB : PROF_FD_SLAB_BWD);
   return STLS_OK;
 }
 

@@ -721,8 +721,9 @@ int stls_pcg_history(stls_handle h, double* out, int max, int* count) {
   return STLS_OK;
 }
 
-static const char* kProfNames[PROF_COUNT] = {"fd_space", "fd_time", "mv_inner1", "mv_inner2", "mv_outer",
-                                             "vec", "reduce", "diff", "fd_slab"};
+static const char* kProfNames[PROF_COUNT] = {"fd_space", "fd_time", "mv_inner1",   "mv_inner2",   "mv_outer",
+                                             "vec_xr",   "reduce",  "diff",        "fd_slab_fwd", "fd_slab_bwd",
+                                             "vec_p",    "misc"};
 
 int stls_set_profiling(stls_handle h, int on) {
   if (!h) { set_error("NULL handle"); return STLS_EINVAL; }

@@ -95,10 +95,13 @@ enum ProfId {
   PROF_MV_INNER1,     // matvec inner stage, d = 2 (space direction 1)
   PROF_MV_INNER2,     // matvec inner stage, d = 3 (space directions 1 and 2)
   PROF_MV_OUTER,      // matvec outer stage (last space direction and time)
-  PROF_VEC,           // PCG vector kernels
+  PROF_VEC,           // PCG update of x and r (with the partial sums of r . r)
   PROF_REDUCE,        // PCG scalar finalisation kernels
   PROF_DIFF,          // differentiation operators (load, transpose, mass, d/dkappa)
-  PROF_FD_SLAB,       // FD slab pass: modes 1 and 2 of every (i3, t) slab
+  PROF_FD_SLAB,       // FD slab pass, forward: modes 1 and 2 of every (i3, t) slab
+  PROF_FD_SLAB_BWD,   // FD slab pass, backward (writes s, partial sums of s . r)
+  PROF_VEC_P,         // PCG direction update p = z + beta p
+  PROF_MISC,          // other elementwise kernels (initial dot, diagonal scaling)
   PROF_COUNT
 };
 

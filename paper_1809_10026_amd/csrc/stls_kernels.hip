@@ -708,7 +708,7 @@ static int launch_diag_scale(stls_ctx* h, const double* x, double* y, const doub
                        nullptr, nullptr, h->gate);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "diag_scale_kernel launch");
-  prof_end(h, PROF_VEC);
+  prof_end(h, PROF_MISC);
   if (nparts) *nparts = blocks;
   return STLS_OK;
 }
@@ -1790,7 +1790,7 @@ int pcg_run(stls_ctx* h, const double* b, double* x, double rtol, int maxit, int
   hipLaunchKernelGGL(init_scalars_kernel, dim3(1), dim3(64), 0, h->stream, h->scal, rtol);
   prof_begin(h);
   hipLaunchKernelGGL(dot_kernel, dim3(nb), dim3(kThreads), 0, h->stream, b, b, N, h->partials);
-  prof_end(h, PROF_VEC);
+  prof_end(h, PROF_MISC);
   if ((st = fin(h, nb, FIN_BNORM, nullptr, 0))) return st;
   if ((st = read_scalars(h))) return st;
   PcgScalars* S = h->scal_host;
@@ -1838,7 +1838,7 @@ int pcg_run(stls_ctx* h, const double* b, double* x, double rtol, int maxit, int
       prof_begin(h);
       hipLaunchKernelGGL(update_p_kernel, dim3(nb), dim3(kThreads), 0, h->stream, h->pvec, h->z, N, h->scal,
                          h->partials, np, par);
-      prof_end(h, PROF_VEC);
+      prof_end(h, PROF_VEC_P);
       if ((e = hipGetLastError()) != hipSuccess) { st = hip_fail(e, "update_p_kernel launch"); break; }
     }
     if ((e = hipEventSynchronize(h->check_ev[par])) != hipSuccess) { st = hip_fail(e, "hipEventSynchronize"); break; }
