@@ -199,6 +199,20 @@ int stls_get_forcing_shape(stls_handle h, int* m, int64_t* nfull);
  * Mbar elsewhere).  f: nfull doubles; F: ndof doubles. */
 int stls_load_apply(stls_handle h, const double* f, double* F);
 
+/* F = B_kappa f exactly as stls_load_apply (same kernels, same order, same
+ * result bit for bit), for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  The call
+ * allocates nothing, host or device: its chain temporaries live in a static
+ * device array of 64 MiB (2^23 doubles) that every device the library runs
+ * on holds until the process ends, looked up once per device at stls_setup.
+ * The temporaries need about 2 * nfull * n_1 / m_1 doubles (e.g. 131^3
+ * forcing coefficients fit); larger problems get STLS_EINVAL with the sizes
+ * in stls_last_error.  Every call on a device shares that device's array:
+ * calls that overlap on one device (two streams, or two host threads) race
+ * and must be serialised by the caller.  f: nfull doubles; F: ndof doubles;
+ * stream-ordered and asynchronous on the handle's stream. */
+int stls_load_apply_noalloc(stls_handle h, const double* f, double* F);
+
 /* gf = B_kappa^T l: l ndof doubles, gf nfull doubles. */
 int stls_load_apply_T(stls_handle h, const double* l, double* gf);
 

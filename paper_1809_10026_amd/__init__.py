@@ -67,6 +67,7 @@ _sig = {
     "stls_profile_reset": (ctypes.c_int, [ctypes.c_void_p]),
     "stls_get_forcing_shape": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, ctypes.POINTER(ctypes.c_int64)]),
     "stls_load_apply": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
+    "stls_load_apply_noalloc": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
     "stls_load_apply_T": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
     "stls_lift_initial": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p]),
     "stls_lift_combine": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_dbl_p]),
@@ -228,6 +229,11 @@ def stls_get_forcing_shape(h, d):
 
 def stls_load_apply(h, nfull, ndof, f, F):
     _check(_lib.stls_load_apply(h, _dev_ptr(f, nfull, "f"), _dev_ptr(F, ndof, "F")), "stls_load_apply")
+
+
+def stls_load_apply_noalloc(h, nfull, ndof, f, F):
+    _check(_lib.stls_load_apply_noalloc(h, _dev_ptr(f, nfull, "f"), _dev_ptr(F, ndof, "F")),
+           "stls_load_apply_noalloc")
 
 
 def stls_load_apply_T(h, nfull, ndof, lam, gf):

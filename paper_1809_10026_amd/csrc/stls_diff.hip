@@ -13,9 +13,18 @@
 
 #include <algorithm>
 #include <functional>
+#include <mutex>
 #include <vector>
 
 #include "stls_internal.h"
+
+// Workspace of the allocation-free entry point (stls_load_apply_noalloc): one
+// copy of this array on every device the library runs on, held from module
+// load until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol); it uses the
+// device address that resolve_noalloc_scratch looks up per device.
+constexpr size_t kNoAllocScratchDoubles = size_t(1) << 23;  // 64 MiB
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
 
 namespace stls {
 
@@ -285,6 +294,27 @@ __global__ __launch_bounds__(kT) void embed_add_kernel(const double* __restrict_
 
 }  // namespace
 
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;  // per device index; nullptr until looked up
+}  // namespace
+
+int resolve_noalloc_scratch(stls_ctx* h) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  h->noalloc_scratch = g_scratch_ptr[dev];
+  return STLS_OK;
+}
+
 }  // namespace stls
 
 using namespace stls;
@@ -310,6 +340,67 @@ int stls_load_apply(stls_handle h, const double* f, double* F) {
   for (auto& t : load_terms(h, false)) {
     if ((st = apply_chain(h, f, F, t.second, t.first, !first, h->ftmp[0], h->ftmp[1]))) return st;
     first = false;
+  }
+  return STLS_OK;
+}
+
+// F = B_kappa f with the chain temporaries in the device's static workspace:
+// the same terms, kernels and launch order as stls_load_apply, without any
+// allocation (host or device).  Each mode product overwrites its whole
+// output, so nothing in the workspace has to start at zero.
+int stls_load_apply_noalloc(stls_handle h, const double* f, double* F) {
+  if (!h || !f || !F) { set_error("bad handle or pointers"); return STLS_EINVAL; }
+  if (!h->bands_ready || !h->noalloc_scratch) {
+    set_error("handle has no device bands or workspace address (stls_setup did not complete)");
+    return STLS_EINVAL;
+  }
+  const int d = h->d, nm = d + 1;
+  // terms of B_kappa: C_t (x) Mbar_s, then -kappa Mbar_t (x) (Gbar_k, Mbar elsewhere)
+  Fac fac[kMaxDim + 1][kMaxDim + 1];
+  double coef[kMaxDim + 1];
+  const int nterm = d + 1;
+  for (int t = 0; t < nterm; ++t) {
+    for (int k = 0; k < d; ++k) fac[t][k] = rect(h->dd[k], (t == k + 1) ? h->dd[k].Gbar : h->dd[k].Mbar);
+    fac[t][d] = rect(h->dd[d], t == 0 ? h->dd[d].Cbar : h->dd[d].Mbar);
+    coef[t] = t == 0 ? 1.0 : -h->kappa;
+  }
+  // sizes of the intermediates: mode k's result goes to t0 (k even) or t1 (k odd)
+  long long need[2] = {0, 0};
+  long long cur[kMaxDim + 1];
+  for (int k = 0; k < nm; ++k) cur[k] = fac[0][k].n_in;
+  for (int k = 0; k + 1 < nm; ++k) {
+    cur[k] = fac[0][k].n_out;
+    long long sz = 1;
+    for (int m = 0; m < nm; ++m) sz *= cur[m];
+    need[k % 2] = std::max(need[k % 2], sz);
+  }
+  const long long off1 = (need[0] + 31) / 32 * 32;  // 256-byte aligned second region
+  if (off1 + need[1] > (long long)kNoAllocScratchDoubles) {
+    set_error("stls_load_apply_noalloc: the chain temporaries need " + std::to_string(off1 + need[1]) +
+              " doubles, more than the static workspace of " + std::to_string(kNoAllocScratchDoubles) +
+              " doubles (64 MiB); use stls_load_apply");
+    return STLS_EINVAL;
+  }
+  double* t0 = h->noalloc_scratch;
+  double* t1 = h->noalloc_scratch + off1;
+  for (int t = 0; t < nterm; ++t) {
+    for (int k = 0; k < nm; ++k) cur[k] = fac[t][k].n_in;
+    const double* in = f;
+    for (int k = 0; k < nm; ++k) {
+      long long L = 1, R = 1;
+      for (int m = 0; m < k; ++m) L *= cur[m];
+      for (int m = k + 1; m < nm; ++m) R *= cur[m];
+      const bool last = k == nm - 1;
+      double* out = last ? F : (k % 2 == 0 ? t0 : t1);
+      const long long total = L * fac[t][k].n_out * R;
+      hipLaunchKernelGGL(band_rect_kernel, dim3(grid_for(total)), dim3(kT), 0, h->stream, in, out, (int)L,
+                         fac[t][k].n_in, fac[t][k].n_out, (int)R, fac[t][k].band, fac[t][k].p, fac[t][k].off,
+                         fac[t][k].trans, last ? coef[t] : 1.0, (last && t > 0) ? 1 : 0);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return hip_fail(e, "band_rect_kernel launch");
+      cur[k] = fac[t][k].n_out;
+      in = out;
+    }
   }
   return STLS_OK;
 }

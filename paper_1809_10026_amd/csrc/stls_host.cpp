@@ -481,8 +481,11 @@ DiagScale diag_scale_args(const stls_ctx* h) {
   return S;
 }
 
-int ensure_diff_operands(stls_ctx* h) {
-  if (h->diff_ready) return STLS_OK;
+// Rectangular (restricted x full) bands of the differentiation and lifting
+// operators: small (n x (2p+1) per band), uploaded once at setup so that the
+// allocation-free entry points find them on the device.
+int upload_diff_bands(stls_ctx* h) {
+  if (h->bands_ready) return STLS_OK;
   int st = STLS_OK;
   h->nfull = 1;
   for (int k = 0; k <= h->d && !st; ++k) {
@@ -498,6 +501,14 @@ int ensure_diff_operands(stls_ctx* h) {
     if (!st) st = dev_upload(&dd.Hbar, D.Hbar.data(), D.Hbar.size(), h->stream);
     if (!st) st = dev_upload(&dd.Dbar, D.Dbar.data(), D.Dbar.size(), h->stream);
   }
+  if (!st) h->bands_ready = true;
+  return st;
+}
+
+// Full-space temporaries of the differentiation operators (first use).
+int ensure_diff_operands(stls_ctx* h) {
+  if (h->diff_ready) return STLS_OK;
+  int st = upload_diff_bands(h);
   if (!st && h->nfull > 2147483647LL) { set_error("forcing space too large"); st = STLS_EINVAL; }
   for (int i = 0; i < 2 && !st; ++i) {
     hipError_t e = hipMalloc((void**)&h->ftmp[i], sizeof(double) * (size_t)h->nfull);
@@ -616,6 +627,8 @@ int stls_setup(int d, const int* nknots, const double* const* knots, const int* 
   }
   if (!st) st = upload_lambda_s(h);
   if (!st) st = upload_diagonals(h);
+  if (!st) st = upload_diff_bands(h);
+  if (!st) st = resolve_noalloc_scratch(h);
   const size_t nb = (size_t)h->ndof * sizeof(double);
   auto alloc = [&](double** p, size_t bytes) {
     if (st) return;

@@ -134,7 +134,9 @@ struct stls_ctx {
   double* ftmp[2] = {nullptr, nullptr};  // full-space temporaries (differentiation ops)
   double* lgrp[4] = {nullptr, nullptr, nullptr, nullptr};  // lifting: one full-space sum per time factor
   int64_t nfull = 0;               // prod of full sizes m_k
-  bool diff_ready = false;
+  bool bands_ready = false;        // rectangular bands on the device (uploaded at setup)
+  bool diff_ready = false;         // and the full-space temporaries allocated
+  double* noalloc_scratch = nullptr;  // this device's static workspace (stls_load_apply_noalloc)
   stls::PcgScalars* scal = nullptr;
   stls::PcgScalars* scal_host = nullptr;  // pinned, 2 slots (convergence checks of alternate iterations)
   hipEvent_t check_ev[2] = {nullptr, nullptr};
@@ -182,7 +184,11 @@ DiagScale diag_scale_args(const stls_ctx* h);
 bool fd_bf16_five_pass_covers(const stls_ctx* h);
 int prec_apply_bf16x3_five_pass(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
                                 int* nparts, bool scale);
+int upload_diff_bands(stls_ctx* h);
 int ensure_diff_operands(stls_ctx* h);
+// Device address of the static workspace of the allocation-free entry points
+// on the current device (looked up once per device; stls_diff.hip).
+int resolve_noalloc_scratch(stls_ctx* h);
 
 // profiling helpers
 void prof_begin(stls_ctx* h);
