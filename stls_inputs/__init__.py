@@ -14,6 +14,7 @@ import numpy as np
 
 __all__ = [
     "uniform_open_knots",
+    "graded_open_knots",
     "problem_knots",
     "uniform_pm1",
     "CONFIGS",
@@ -33,6 +34,28 @@ def uniform_open_knots(n_el: int, p: int) -> np.ndarray:
     if n_el < 1 or p < 0:
         raise ValueError("n_el >= 1 and p >= 0 required")
     inner = [float(i) / float(n_el) for i in range(1, n_el)]
+    return np.array([0.0] * (p + 1) + inner + [1.0] * (p + 1), dtype=np.float64)
+
+
+def graded_open_knots(n_el: int, p: int, mult: int = 1, seed: int = 0) -> np.ndarray:
+    """Open knot vector on [0, 1] with ``n_el`` non-empty elements of uneven
+    length and one interior knot of multiplicity ``mult`` (§2.1: the
+    regularity at a knot is p minus its multiplicity).
+
+    Element lengths are drawn from U[0.4, 1.6] with ``default_rng(seed)``
+    and normalised to sum to one; the breakpoints are their cumulative sums
+    (the last one set to 1 exactly).  The interior breakpoint nearest to the
+    middle is repeated ``mult`` times.
+    """
+    if n_el < 2 or p < 0 or mult < 1:
+        raise ValueError("n_el >= 2, p >= 0 and mult >= 1 required")
+    rng = np.random.default_rng(seed)
+    h = rng.uniform(0.4, 1.6, size=n_el)
+    b = np.cumsum(h / h.sum())
+    b[-1] = 1.0
+    inner = [float(v) for v in b[:-1]]
+    mid = n_el // 2 - 1
+    inner = inner[:mid] + [inner[mid]] * mult + inner[mid + 1:]
     return np.array([0.0] * (p + 1) + inner + [1.0] * (p + 1), dtype=np.float64)
 
 
