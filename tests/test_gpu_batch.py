@@ -143,7 +143,12 @@ def test_d1_batch_matches_single_problems():
 
 def test_full_uneven_batch_converges():
     """256 problems: n_el per direction uniform on 16..96, p uniform on {2..5},
-    kappa log-uniform on [0.1, 10], right-hand sides U[-1,1] (seeds 20180927 + i)."""
+    kappa log-uniform on [0.1, 10], right-hand sides U[-1,1] (seeds 20180927 + i).
+    Every problem's batched matvec and FD application is compared with the
+    oracle's (FD: backward error at rounding level, forward difference within
+    the first-order bound eps * max lambda_max / lambda_min of the pencils),
+    and every batched solution's true residual is taken with the oracle's
+    matvec; three problems are also solved standalone."""
     nel, p, kappa = batch_params()
     probs = []
     for i in range(len(p)):
@@ -155,6 +160,49 @@ def test_full_uneven_batch_converges():
     bt = to_dev(b)
     x, its, rels = B.solve(bt, rtol=1e-8, maxit=500)
     assert len(its) == 256 and max(rels) <= 1e-8 and min(its) >= 1
+    # every problem against the oracle: matvec and FD applied to a seeded
+    # vector, and the true residual of the batched solution (oracle workers
+    # in separate processes: its assembly takes ~0.4 s per problem)
+    import multiprocessing as mp
+    import os
+
+    from tests.oracle_batch import check_problem
+    v = uniform_pm1(B.total, 68)
+    vd = to_dev(v)
+    yb = to_host(B.matvec(vd))
+    sb = to_host(B.prec_apply(vd))
+    xh = to_host(x)
+    jobs = [(nel[i], int(p[i]), float(kappa[i]), v[off[i]:off[i + 1]], yb[off[i]:off[i + 1]], sb[off[i]:off[i + 1]],
+             b[off[i]:off[i + 1]], xh[off[i]:off[i + 1]]) for i in range(len(probs))]
+    workers = max(1, min(16, os.cpu_count() or 1))
+    # one BLAS thread per worker (the workers start with this environment):
+    # a worker pool of multi-threaded BLAS libraries oversubscribes the cores
+    blas = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in blas}
+    os.environ.update({k: "1" for k in blas})
+    try:
+        pool = mp.get_context("spawn").Pool(workers)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    res = []
+    with pool:
+        for r in pool.imap(check_problem, jobs, chunksize=2):
+            res.append(r)
+            if len(res) % 32 == 0:
+                print(f"oracle checks: {len(res)} of {len(jobs)} problems", flush=True)
+    worst = {k: max(r[k] for r in res) for k in ("matvec", "fd_backward", "true_relres")}
+    fwd = max(r["fd_forward"] / r["fd_bound"] for r in res)
+    print(f"256 problems vs oracle: matvec {worst['matvec']:.2e}, FD backward {worst['fd_backward']:.2e}, "
+          f"FD forward / bound {fwd:.2e}, true relres {worst['true_relres']:.2e}", flush=True)
+    for i, r in enumerate(res):
+        assert r["matvec"] < 1e-13, (i, r)
+        assert r["fd_backward"] < 1e-14, (i, r)
+        assert r["fd_forward"] < max(1e-12, r["fd_bound"]), (i, r)
+        assert r["true_relres"] < 2e-8, (i, r)
     # batch invariant on sampled problems: standalone solves agree
     for i in (0, 97, 255):
         knots, degs, kap = probs[i]

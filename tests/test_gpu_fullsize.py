@@ -5,11 +5,10 @@ right-hand side U[-1, 1] with the benchmark's seed.
 The oracle applies the matvec, the FD preconditioner and the initial-data
 lifting to the whole vector in a few seconds, so those are compared entry by
 entry; the general lifting is checked by its identity with the matvec on
-zero-data functions; a full oracle PCG
-would take about a minute, so the solves are checked by properties that hold
-at any size: the oracle's matvec gives the true residual of the GPU solution,
-and the solutions of the different FD precisions agree to the solve
-tolerance.  Tolerances as in the small-size parity tests.
+zero-data functions; the solves of every FD precision are compared with the
+oracle's own FP64 FD-PCG solution (about 17 s on the host cores) and their
+true residuals are taken with the oracle's matvec.  Tolerances as in the
+small-size parity tests.
 """
 import numpy as np
 import pytest
@@ -64,10 +63,14 @@ def _eig_bounds(P):
 def test_fullsize_prec_apply(full, mode, scaled, tol):
     """FP64: the backward error ||P s - r|| / (||P|| ||s||) is at rounding
     level (||P|| bounded above through the factors' eigenvalues), and the
-    difference to the oracle is within 10 eps cond(P) (cond(P) <= 7e11 here:
-    the forward difference of two backward-stable solves can be that large,
-    so the backward error is the sharp check).  FP32 / BF16x3: the product
-    error bounds of the small-size tests."""
+    forward difference to the oracle is within 4 eps max_k lambda_max /
+    lambda_min over the univariate pencils (5.6e-8 here; measured 3.9e-11).
+    Both sides apply U Lambda^-1 U^T with eigenpairs from backward-stable
+    eigensolvers, whose eigenvalues carry absolute errors ~eps lambda_max;
+    after the division the low modes carry relative errors up to
+    eps lambda_max / lambda_min, which bounds the forward difference to first
+    order (an FP32 product anywhere in the chain, ~1e-6, fails it).
+    FP32 / BF16x3: the product error bounds of the small-size tests."""
     S, P, F = full
     S.set_fd_precision(mode)
     S.set_fd_scaling(scaled)
@@ -87,9 +90,12 @@ def test_fullsize_prec_apply(full, mode, scaled, tol):
         else:
             Ps = osys.vec(P.prec_matvec(s))
         backward = np.linalg.norm(Ps - r) / (hi * np.linalg.norm(s))
-        print(f"backward {backward:.2e} forward {rel_err(s, ref):.2e} cond bound {hi / lo:.2e}", flush=True)
+        spread = max(l.max() / l.min() for l, _ in F.eig_space + [F.eig_time])
+        bound = 4 * np.finfo(float).eps * spread
+        print(f"backward {backward:.2e} forward {rel_err(s, ref):.2e} first-order bound {bound:.2e} "
+              f"(cond(P) bound {hi / lo:.2e})", flush=True)
         assert backward < 1e-14
-        assert rel_err(s, ref) < max(1e-12, 10 * np.finfo(float).eps * hi / lo)
+        assert rel_err(s, ref) < bound
     finally:
         S.set_fd_precision(0)
         S.set_fd_scaling(False)
@@ -97,8 +103,10 @@ def test_fullsize_prec_apply(full, mode, scaled, tol):
 
 def test_fullsize_pcg(full):
     """The benchmark's solve in every mode: true residual by the oracle's
-    matvec, and agreement with the FP64 solution."""
-    S, P, _ = full
+    matvec, and every solution compared entry by entry with the oracle's own
+    FP64 FD-PCG solution of the same system (about 17 s on the host cores)."""
+    from oracle import pcg as opcg
+    S, P, F = full
     b = uniform_pm1(S.ndof, CFG["seed"])
     bd = to_dev(b)
     sols = {}
@@ -115,9 +123,12 @@ def test_fullsize_pcg(full):
     finally:
         S.set_fd_precision(0)
         S.set_fd_scaling(False)
-    ref = sols[(0, False)]
+    x_ref, info = opcg.pcg(lambda v: osys.vec(P.matvec(v)), lambda v: osys.vec(F.apply(v)), b, CFG["rtol"])
+    assert abs(info["iters"] - 17) <= 1
     for key, xo in sols.items():
-        assert rel_err(xo, ref) < 2 * 3 * 10 * CFG["rtol"], key
+        err = rel_err(xo, x_ref)
+        print(f"mode {key}: vs oracle solution rel {err:.2e} max abs {np.abs(xo - x_ref).max():.2e}", flush=True)
+        assert err < 2 * 3 * 10 * CFG["rtol"], key
 
 
 @pytest.mark.parametrize("rhs", ["manufactured", "random"])
