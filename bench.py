@@ -383,19 +383,33 @@ def gpu_batch(stls, torch, steps=3):
     b = torch.as_tensor(np.concatenate([uniform_pm1(off[i + 1] - off[i], 20180927 + i)
                                         for i in range(len(probs))])).cuda()
     x = torch.empty_like(b)
-    B.solve(b, 1e-8, 500, out=x)
-    torch.cuda.synchronize()
+
+    def timed():
+        B.solve(b, 1e-8, 500, out=x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, its, rels = B.solve(b, 1e-8, 500, out=x)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, its, rels
+
+    dt_default, _, _ = timed()
+    default_tuning = B.tuning
+    # autotuner: work-item shapes and launch geometry timed on this batch (no
+    # cache here: the bench always measures)
     t = time.perf_counter()
-    for _ in range(steps):
-        _, its, rels = B.solve(b, 1e-8, 500, out=x)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t) / steps
-    log(f"batch: {dt*1e3:.1f} ms for {B.total} unknowns, {max(its)} iterations")
+    B.autotune()
+    tune_s = time.perf_counter() - t
+    dt, its, rels = timed()
+    log(f"batch: {dt*1e3:.1f} ms tuned ({dt_default*1e3:.1f} ms default shapes) for {B.total} unknowns, "
+        f"{max(its)} iterations; tuning {B.tuning}")
     return {"workload": "256 independent d=2 problems, n_el per direction U{16..96}, p U{2..5}, "
                         "kappa 10^U(-1,1), RHS U[-1,1] (seeds 20180927+i), rtol 1e-8, FP64 FD",
             "total_dof": int(B.total), "seconds": dt, "dof_per_s": B.total / dt, "max_iters": int(max(its)),
             "iteration_ms": dt / max(its) * 1e3, "graph_replay": bool(B.graph_used), "setup_s": setup_s,
-            "max_relres": float(max(rels))}
+            "max_relres": float(max(rels)),
+            "autotune": {"seconds": tune_s, "tuning": B.tuning, "default_tuning": default_tuning,
+                         "default_seconds": dt_default}}
 
 
 def gpu_lifting(stls, torch, knots, degs, reps=20):

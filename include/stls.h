@@ -275,8 +275,9 @@ int stls_dkappa_terms(stls_handle h, const double* f, const double* u, const dou
  * Synchronises. */
 int stls_dot(stls_handle h, const double* a, const double* b, int64_t n, double* out);
 
-/* e = u - ustar, q = (M_t (x) M_s) e (device, ndof), *loss (host) = e . q
- * (squared L2 norm of u_h - u*_h over the space-time cylinder).  Synchronises. */
+/* e = u - ustar, *loss (host) = e^T (M_t (x) M_s) e (squared L2 norm of
+ * u_h - u*_h over the space-time cylinder) and q = 2 (M_t (x) M_s) e, its
+ * gradient with respect to u (device, ndof).  Synchronises. */
 int stls_misfit(stls_handle h, const double* u, const double* ustar, double* q, double* loss);
 
 /* ------------------------------------------------------------------------
@@ -332,6 +333,42 @@ int stls_batch_set_graph(stls_batch_handle b, int on);
 /* 1 if the last stls_batch_pcg_solve replayed a captured graph, 0 if it
  * launched the kernels directly, STLS_EINVAL for a NULL handle. */
 int stls_batch_graph_used(stls_batch_handle b);
+
+/* Work-item shapes and launch geometry of the batched kernels (one int each,
+ * in this order).  Results do not depend on them except through the order
+ * of the partial sums of dot products (rounding). */
+typedef enum stls_batch_tune_field {
+  STLS_TUNE_VEC_CHUNK = 0,   /* elements per vector work item: 256..2^20, multiple of 256 */
+  STLS_TUNE_INNER_STEPS = 1, /* column steps per inner-stage (d = 2) work item: 1..64 */
+  STLS_TUNE_OUTER_CHUNK = 2, /* time slices per outer-stage work item (at most): 1..65536 */
+  STLS_TUNE_GRID_FD = 3,     /* workgroups per launch (caps): FD passes, */
+  STLS_TUNE_GRID_INNER = 4,  /*   inner stage, */
+  STLS_TUNE_GRID_OUTER = 5,  /*   outer stage, */
+  STLS_TUNE_GRID_VEC = 6,    /*   vector kernels: 1..65536 */
+  STLS_TUNE_GRAPH_DEPTH = 7, /* PCG iterations per captured graph launch (host checks
+                                convergence once per launch; never more than maxit): 1..64 */
+  STLS_TUNE_COUNT = 8
+} stls_batch_tune_field;
+
+/* vals: STLS_TUNE_COUNT ints. */
+int stls_batch_get_tuning(stls_batch_handle b, int* vals);
+/* Validates every value (STLS_EINVAL if out of range), waits for the
+ * batch's streams and rebuilds the work lists.  Synchronises. */
+int stls_batch_set_tuning(stls_batch_handle b, const int* vals);
+
+/* Autotuner: picks the tuning fields for this batch by timing candidates
+ * with HIP events on the batch's stream, one group of fields at a time
+ * (vector chunk and grid; inner steps and grid; outer time chunk and grid;
+ * FD grid; then the graph depth by timing whole solves of a right-hand side
+ * of ones on scratch vectors), and applies the fastest.  With cache_path
+ * (a JSON file, created if missing) a choice stored under the same key (the
+ * batch kernels' source hash, the device architecture and a hash of every
+ * problem's sizes and degree) is applied without measuring, and a new choice
+ * is stored.  *measured (may be NULL) = 1 if timings were taken, 0 if the
+ * cache supplied the choice.  The batch's work vectors and PCG scalars are
+ * overwritten; synchronises.  STLS_EINVAL for an unreadable or malformed
+ * cache file. */
+int stls_batch_autotune(stls_batch_handle b, const char* cache_path, int* measured);
 
 /* Per-kernel timing with HIP events on the handle's stream (0 = off). */
 int stls_set_profiling(stls_handle h, int on);

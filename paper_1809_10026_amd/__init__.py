@@ -40,6 +40,9 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 STLS_OK, STLS_EINVAL, STLS_ENOMEM, STLS_EHIP, STLS_ENOCONV, STLS_ENAN, STLS_EBREAKDOWN = 0, -1, -2, -3, -4, -5, -6
 STLS_FD_FP64, STLS_FD_FP32, STLS_FD_BF16X3 = 0, 1, 2
+# batch tuning fields, in the order of enum stls_batch_tune_field
+TUNE_FIELDS = ("vec_chunk", "inner_steps", "outer_chunk", "grid_fd", "grid_inner", "grid_outer", "grid_vec",
+               "graph_depth")
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 _c_dbl_p = ctypes.c_void_p
@@ -90,6 +93,9 @@ _sig = {
                                             _c_int_p, ctypes.POINTER(ctypes.c_double)]),
     "stls_batch_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "stls_batch_graph_used": (ctypes.c_int, [ctypes.c_void_p]),
+    "stls_batch_get_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
+    "stls_batch_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
+    "stls_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]),
     "stls_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "stls_last_error": (ctypes.c_char_p, []),
 }
@@ -390,6 +396,29 @@ class Batch:
         _check(min(v, 0), "stls_batch_graph_used")
         return bool(v)
 
+    @property
+    def tuning(self):
+        """Work-item shapes and launch geometry, a dict keyed by TUNE_FIELDS."""
+        vals = (ctypes.c_int * len(TUNE_FIELDS))()
+        _check(_lib.stls_batch_get_tuning(self._h, vals), "stls_batch_get_tuning")
+        return dict(zip(TUNE_FIELDS, list(vals)))
+
+    @tuning.setter
+    def tuning(self, values):
+        cur = self.tuning
+        cur.update(values)
+        vals = (ctypes.c_int * len(TUNE_FIELDS))(*[int(cur[k]) for k in TUNE_FIELDS])
+        _check(_lib.stls_batch_set_tuning(self._h, vals), "stls_batch_set_tuning")
+
+    def autotune(self, cache_path=None):
+        """Pick the tuning by timing candidates (or reuse the choice stored in
+        the JSON file ``cache_path`` under this batch's key).  Returns True if
+        timings were taken, False if the cache supplied the choice."""
+        measured = ctypes.c_int(0)
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(_lib.stls_batch_autotune(self._h, path, ctypes.byref(measured)), "stls_batch_autotune")
+        return bool(measured.value)
+
 
 # ---------------------------------------------------------------------------
 class Solver:
@@ -532,6 +561,7 @@ class Solver:
         return stls_dot(self._h, a, b)
 
     def misfit(self, u, ustar):
+        """(loss, q): loss = (u - u*)^T M_Q (u - u*) and q = 2 M_Q (u - u*), its gradient."""
         q = self._empty()
         return stls_misfit(self._h, self.ndof, u, ustar, q), q
 

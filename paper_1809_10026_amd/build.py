@@ -30,6 +30,17 @@ def hipcc() -> str:
     return exe
 
 
+def batch_source_hash() -> str:
+    """SHA-256 of the batched kernels' sources: the key under which the
+    batch autotuner caches its choices (a changed kernel is re-tuned)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("stls_batch.hip", "stls_buf.h", "stls_internal.h"):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     """Compile every translation unit in parallel, then link libstls.so."""
     tmp = LIB + ".tmp"
@@ -37,7 +48,8 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(CSRC, src.rsplit(".", 1)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc(), *HIP_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        defs = [f'-DSTLS_BATCH_SOURCE_HASH="{batch_source_hash()}"'] if src == "stls_batch.hip" else []
+        cmd = [hipcc(), *HIP_FLAGS, *lang, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         jobs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))

@@ -13,10 +13,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cmath>
-#include <cstring>
-#include <string>
 #include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <functional>
+#include <map>
+#include <sstream>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -31,17 +36,14 @@ constexpr int kT = 256;
 constexpr int kBCols = 64;            // FD panel width
 constexpr int kBLdx = kBCols + 1;     // panel LDS row stride (static LDS stays below 64 KB)
 constexpr int kBNM = 7;               // max 16-row tiles per direction (n <= 112)
-constexpr int kVecChunk = 4096;       // elements per vector work item
-constexpr int kInSteps = 8;           // column steps per inner-stage work item
 constexpr int kOLb = 16, kOMaxTd = 16, kOSlots = 2;
-constexpr int kOChunk = 32;            // outer stage: time slices per work item (at most)
 
 typedef double d4b_t __attribute__((ext_vector_type(4)));
 
 // Device descriptor of one problem.
 struct BProb {
   long long off;   // offset of the problem's vectors in the concatenated buffers
-  int N, ns, d, pad0;
+  int N, ns, d, vchunk;  // vchunk: elements per vector work item
   int n[3], p[3], npad[3];
   const double* Af[3];
   const double* Ab[3];
@@ -51,7 +53,7 @@ struct BProb {
   const double* lam_t;
   const double* lam_s;
   double k2, kw;
-  int Td, nlb, ntd, nchunk, Tc, pad1;
+  int Td, nlb, ntd, nchunk, Tc, insteps;  // insteps: column steps per inner-stage work item
 };
 
 struct Item {
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(kT) void bfd_kernel(const double* __restrict__ X, d
 // contiguous columns of n1 entries, for the problems of degree PP.  Thread t
 // of a workgroup owns row i = t mod n1 of the three banded operators (its
 // 3 (2PP+1) band entries stay in registers for the whole item) and column
-// lane t / n1 of G = kT / n1; an item is kInSteps column steps of G columns.
+// lane t / n1 of G = kT / n1; an item is B.insteps column steps of G columns.
 // The 2PP+1 taps are unrolled with clamped columns (band entries outside the
 // matrix are stored as zeros, so the clamped reads add nothing).
 template <int PP>
@@ -277,9 +279,9 @@ __global__ __launch_bounds__(kT) void binner1_kernel(const double* __restrict__ 
     const __amdgpu_buffer_rsrc_t rA = buf_rsrc(A + B.off, bytes);
     const __amdgpu_buffer_rsrc_t rB = buf_rsrc(Bo + B.off, bytes);
     const __amdgpu_buffer_rsrc_t rC = buf_rsrc(C + B.off, bytes);
-    const int cb = I.idx * G * kInSteps + cg;
+    const int cb = I.idx * G * B.insteps + cg;
 #pragma unroll 2
-    for (int s = 0; s < kInSteps; ++s) {
+    for (int s = 0; s < B.insteps; ++s) {
       const int c = cb + s * G;
       const bool ok = act && c < ncols;
       const int colb = (int)sizeof(double) * min(c, ncols - 1) * n1;
@@ -464,8 +466,8 @@ __global__ __launch_bounds__(kT) void bvec_kernel(int kind, double* __restrict__
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const Item I = items[it];
     const BProb& B = P[I.prob];
-    const size_t e0 = B.off + (size_t)I.idx * kVecChunk;
-    const size_t e1 = B.off + std::min<size_t>((size_t)(I.idx + 1) * kVecChunk, (size_t)B.N);
+    const size_t e0 = B.off + (size_t)I.idx * B.vchunk;
+    const size_t e1 = B.off + std::min<size_t>((size_t)(I.idx + 1) * B.vchunk, (size_t)B.N);
     double s = 0.0;
     if (kind == BV_INIT) {  // x = 0, r = b; partial sums of b.b
       for (size_t e = e0 + threadIdx.x; e < e1; e += kT) {
@@ -501,8 +503,8 @@ __global__ void bcopy_kernel(double* __restrict__ dst, const double* __restrict_
     const Item I = items[it];
     if (skip(S, I.prob)) continue;
     const BProb& B = P[I.prob];
-    const size_t e0 = B.off + (size_t)I.idx * kVecChunk;
-    const size_t e1 = B.off + std::min<size_t>((size_t)(I.idx + 1) * kVecChunk, (size_t)B.N);
+    const size_t e0 = B.off + (size_t)I.idx * B.vchunk;
+    const size_t e1 = B.off + std::min<size_t>((size_t)(I.idx + 1) * B.vchunk, (size_t)B.N);
     for (size_t e = e0 + threadIdx.x; e < e1; e += kT) dst[e] = src[e];
   }
 }
@@ -560,7 +562,9 @@ int upload_vec(T** dst, const std::vector<T>& v, hipStream_t st) {
     set_error("hipMalloc (batch)");
     return STLS_ENOMEM;
   }
-  if (!v.empty() && hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess) {
+  // synchronised: the host vector is a temporary of the caller
+  if (!v.empty() && (hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess ||
+                     hipStreamSynchronize(st) != hipSuccess)) {
     set_error("hipMemcpyAsync (batch)");
     return STLS_EHIP;
   }
@@ -573,6 +577,22 @@ struct ItemList {
   int* beg = nullptr;  // per problem, into this list
   int* end = nullptr;
 };
+
+// Work-item shapes and launch geometry of the batched kernels (chosen by
+// stls_batch_autotune; the defaults are the shapes measured best on the
+// 256-problem uneven batch by hand).  Field order = enum stls_batch_tune_field.
+struct BatchTuning {
+  int vec_chunk = 4096;   // elements per vector work item
+  int inner_steps = 8;    // column steps per inner-stage work item
+  int outer_chunk = 32;   // time slices per outer-stage work item (at most)
+  int grid_fd = 2048;     // workgroup caps per launch
+  int grid_inner = 2048;
+  int grid_outer = 2048;
+  int grid_vec = 2048;
+  int graph_depth = 1;    // PCG iterations per captured graph launch
+};
+constexpr int kTuneFields = 8;
+static_assert(sizeof(BatchTuning) == kTuneFields * sizeof(int), "tuning fields");
 
 }  // namespace
 
@@ -609,6 +629,7 @@ struct stls_batch_ctx {
   hipStream_t solve_stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   int graph_used = 0;  // 1 if the last solve replayed a captured graph
+  BatchTuning tune;
 };
 
 namespace {
@@ -659,7 +680,96 @@ void free_batch(stls_batch_ctx* B) {
   delete B;
 }
 
-int grid_items(int n) { return std::max(1, std::min(n, 256 * 8)); }
+// (Re)build the work lists whose item shapes the tuning sets: vector chunks,
+// inner-stage column steps and outer-stage time chunks; upload the problem
+// descriptors carrying those shapes; size the partial-sum buffer.  The
+// stream must be idle (no enqueued kernel reads the old lists).
+int build_tuned_lists(stls_batch_ctx* B) {
+  const BatchTuning& T = B->tune;
+  const int nprob = B->nprob, d = B->d;
+  free_list(B->vec);
+  for (auto& L : B->inner) free_list(L);
+  for (auto& L : B->outer) free_list(L);
+  free_list(B->outer_all);
+  B->inner.clear();
+  B->inner_p.clear();
+  B->outer.clear();
+  B->outer_p.clear();
+  B->outer_base.clear();
+  std::vector<int> cnt_vec(nprob), cnt_in(nprob), cnt_outer(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    BProb& P = B->hdesc[i];
+    const int nt = P.n[d];
+    P.vchunk = T.vec_chunk;
+    P.insteps = T.inner_steps;
+    P.nchunk = (nt + T.outer_chunk - 1) / T.outer_chunk;  // time chunks (each re-reads 2p halo slices)
+    P.Tc = (nt + P.nchunk - 1) / P.nchunk;
+    cnt_outer[i] = P.nlb * P.ntd * P.nchunk;
+    cnt_vec[i] = (P.N + P.vchunk - 1) / P.vchunk;
+    const int G = kT / P.n[0], ncols = P.N / P.n[0];  // n[0] <= 112: G >= 2
+    cnt_in[i] = (ncols + G * P.insteps - 1) / (G * P.insteps);
+  }
+  if (hipMemcpyAsync(B->desc, B->hdesc.data(), sizeof(BProb) * nprob, hipMemcpyHostToDevice, B->stream) !=
+      hipSuccess) {
+    set_error("hipMemcpyAsync (batch descriptors)");
+    return STLS_EHIP;
+  }
+  int st = make_list(B, B->vec, cnt_vec);
+  std::vector<int> uniq;
+  for (int i = 0; i < nprob; ++i) uniq.push_back(B->hdesc[i].p[0]);
+  std::sort(uniq.begin(), uniq.end());
+  uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+  if (!st && d == 2) {  // inner items grouped by degree
+    for (int p : uniq) {
+      std::vector<int> members;
+      for (int i = 0; i < nprob; ++i)
+        if (B->hdesc[i].p[0] == p) members.push_back(i);
+      ItemList L;
+      if ((st = make_list(B, L, cnt_in, &members))) break;
+      B->inner.push_back(L);
+      B->inner_p.push_back(p);
+    }
+  }
+  // outer items grouped by degree; the concatenated list fixes the partial ranges
+  if (!st) {
+    std::vector<int> order;
+    int base = 0;
+    for (int p : uniq) {
+      std::vector<int> members;
+      for (int i = 0; i < nprob; ++i)
+        if (B->hdesc[i].p[0] == p) members.push_back(i);
+      ItemList L;
+      if ((st = make_list(B, L, cnt_outer, &members))) break;
+      B->outer.push_back(L);
+      B->outer_p.push_back(p);
+      B->outer_base.push_back(base);
+      base += L.count;
+      for (int m : members) order.push_back(m);
+    }
+    if (!st) st = make_list(B, B->outer_all, cnt_outer, &order);
+  }
+  int cap = 0;
+  for (int k = 0; k <= d; ++k) cap = std::max(cap, B->fd[k].count);
+  cap = std::max({cap, B->vec.count, B->outer_all.count, 1});
+  if (!st && cap > B->partials_cap) {
+    if (B->partials) (void)hipFree(B->partials);
+    B->partials = nullptr;
+    B->partials_cap = 0;
+    if (hipMalloc((void**)&B->partials, sizeof(double) * cap) != hipSuccess) {
+      set_error("hipMalloc (batch partial sums)");
+      st = STLS_ENOMEM;
+    } else {
+      B->partials_cap = cap;
+    }
+  }
+  if (!st && hipStreamSynchronize(B->stream) != hipSuccess) {
+    set_error("hipStreamSynchronize (batch lists)");
+    st = STLS_EHIP;
+  }
+  return st;
+}
+
+int grid_items(int n, int cap) { return std::max(1, std::min(n, cap)); }
 
 int bfin(stls_batch_ctx* B, const ItemList& L, int kind, double rtol) {
   hipLaunchKernelGGL(bfinalize_kernel, dim3(B->nprob), dim3(kT), 0, B->stream, B->partials, L.beg, L.end, B->S, kind,
@@ -687,7 +797,7 @@ int bfd_pass(stls_batch_ctx* B, int k, const double* in, double* out, int bwd, c
       default: set_error("batch: direction too large for the FD kernel"); return STLS_EINVAL;
     }
     const size_t shmem = sizeof(double) * (size_t)nm * 16 * kBLdx;
-    hipLaunchKernelGGL(kern, dim3(grid_items(count)), dim3(kT), shmem, B->stream, in, out, B->desc,
+    hipLaunchKernelGGL(kern, dim3(grid_items(count, B->tune.grid_fd)), dim3(kT), shmem, B->stream, in, out, B->desc,
                        B->fd[k].dev + first, count, first, k, bwd, B->S, dotv, B->partials);
   }
   const hipError_t e = hipGetLastError();
@@ -750,7 +860,8 @@ int bmatvec(stls_batch_ctx* B, const double* x, double* y, const double* dotv) {
         case 6: kern = binner1_kernel<6>; break;
         default: set_error("batch degree not supported"); return STLS_EINVAL;
       }
-      hipLaunchKernelGGL(kern, dim3(grid_items(L.count)), dim3(kT), 0, st, x, B->buf[6], B->buf[7], B->buf[8],
+      hipLaunchKernelGGL(kern, dim3(grid_items(L.count, B->tune.grid_inner)), dim3(kT), 0, st, x, B->buf[6], B->buf[7],
+                         B->buf[8],
                          B->desc, L.dev, L.count, B->S);
     }
     A = B->buf[6];
@@ -772,7 +883,8 @@ int bmatvec(stls_batch_ctx* B, const double* x, double* y, const double* dotv) {
       case 6: kern = outer_instance<6>(B->d == 2, dotv != nullptr); break;
       default: set_error("batch degree not supported"); return STLS_EINVAL;
     }
-    hipLaunchKernelGGL(kern, dim3(grid_items(L.count)), dim3(kT), 0, st, A, Bv, C, y, B->desc, L.dev, L.count, B->S,
+    hipLaunchKernelGGL(kern, dim3(grid_items(L.count, B->tune.grid_outer)), dim3(kT), 0, st, A, Bv, C, y, B->desc, L.dev,
+                       L.count, B->S,
                        dotv, parts);
   }
   hipError_t e = hipGetLastError();
@@ -830,12 +942,11 @@ int stls_batch_setup(int nprob, int d, const int* nknots, const double* const* k
       free_batch(B);
       return st;
     }
-  // descriptors, offsets, work lists
+  // descriptors, offsets and the FD work lists (independent of the tuning)
   B->off.assign(nprob + 1, 0);
   B->hdesc.resize(nprob);
-  std::vector<int> cnt_vec(nprob), cnt_in(nprob), cnt_fd[4];
+  std::vector<int> cnt_fd[4];
   for (int k = 0; k <= d; ++k) cnt_fd[k].assign(nprob, 0);
-  std::vector<int> cnt_outer(nprob);
   for (int i = 0; i < nprob; ++i) {
     stls_ctx* h = B->probs[i];
     BProb& P = B->hdesc[i];
@@ -866,22 +977,15 @@ int stls_batch_setup(int nprob, int d, const int* nknots, const double* const* k
     P.lam_s = h->lam_s;
     P.k2 = h->kappa * h->kappa;
     P.kw = h->kappa * h->dir[d].wend;
-    const int L = d == 2 ? P.n[0] : 1, nd = P.n[d - 1], nt = P.n[d];
+    const int L = d == 2 ? P.n[0] : 1, nd = P.n[d - 1];
     P.ntd = (nd + kOMaxTd - 1) / kOMaxTd;
     P.Td = (nd + P.ntd - 1) / P.ntd;
     P.nlb = (L + kOLb - 1) / kOLb;
-    P.nchunk = (nt + kOChunk - 1) / kOChunk;  // time chunks (each re-reads 2p halo slices)
-    P.Tc = (nt + P.nchunk - 1) / P.nchunk;
-    cnt_outer[i] = P.nlb * P.ntd * P.nchunk;
-    cnt_vec[i] = (P.N + kVecChunk - 1) / kVecChunk;
-    {
-      const int G = kT / P.n[0], ncols = P.N / P.n[0];  // n[0] <= 112: G >= 2
-      cnt_in[i] = (ncols + G * kInSteps - 1) / (G * kInSteps);
-    }
     B->off[i + 1] = B->off[i] + P.N;
   }
   B->total = B->off[nprob];
-  int st = upload_vec(&B->desc, B->hdesc, B->stream);
+  int st = STLS_OK;
+  if (hipMalloc((void**)&B->desc, sizeof(BProb) * nprob) != hipSuccess) { set_error("hipMalloc"); st = STLS_ENOMEM; }
   // FD items of each pass ordered by the direction's padded size, one group
   // (kernel instance with that many tiles) per size
   for (int k = 0; k <= d && !st; ++k) {
@@ -899,50 +1003,8 @@ int stls_batch_setup(int nprob, int d, const int* nknots, const double* const* k
       first += count;
     }
   }
-  if (!st) st = make_list(B, B->vec, cnt_vec);
-  if (!st && d == 2) {  // inner items grouped by degree
-    std::vector<int> uniq;
-    for (int i = 0; i < nprob; ++i) uniq.push_back(B->hdesc[i].p[0]);
-    std::sort(uniq.begin(), uniq.end());
-    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
-    for (int p : uniq) {
-      std::vector<int> members;
-      for (int i = 0; i < nprob; ++i)
-        if (B->hdesc[i].p[0] == p) members.push_back(i);
-      ItemList L;
-      if ((st = make_list(B, L, cnt_in, &members))) break;
-      B->inner.push_back(L);
-      B->inner_p.push_back(p);
-    }
-  }
-  // outer items grouped by degree; the concatenated list fixes the partial ranges
-  if (!st) {
-    std::vector<int> degs;
-    for (int i = 0; i < nprob; ++i) degs.push_back(B->hdesc[i].p[0]);
-    std::vector<int> uniq(degs);
-    std::sort(uniq.begin(), uniq.end());
-    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
-    std::vector<int> order;
-    int base = 0;
-    for (int p : uniq) {
-      std::vector<int> members;
-      for (int i = 0; i < nprob; ++i)
-        if (degs[i] == p) members.push_back(i);
-      ItemList L;
-      if ((st = make_list(B, L, cnt_outer, &members))) break;
-      B->outer.push_back(L);
-      B->outer_p.push_back(p);
-      B->outer_base.push_back(base);
-      base += L.count;
-      for (int m : members) order.push_back(m);
-    }
-    if (!st) st = make_list(B, B->outer_all, cnt_outer, &order);
-  }
-  int cap = 0;
-  for (int k = 0; k <= d; ++k) cap = std::max(cap, B->fd[k].count);
-  cap = std::max({cap, B->vec.count, B->outer_all.count, 1});
-  B->partials_cap = cap;
-  if (!st && hipMalloc((void**)&B->partials, sizeof(double) * cap) != hipSuccess) { set_error("hipMalloc"); st = STLS_ENOMEM; }
+  // vector, inner and outer work lists (shaped by the tuning) and partials
+  if (!st) st = build_tuned_lists(B);
   for (int i = 0; i < 9 && !st; ++i)
     if (hipMalloc((void**)&B->buf[i], sizeof(double) * std::max<int64_t>(1, B->total)) != hipSuccess) {
       set_error("hipMalloc batch vectors");
@@ -991,13 +1053,15 @@ int stls_batch_problem(stls_batch_handle B, int i, stls_handle* h) {
 
 int stls_batch_matvec(stls_batch_handle B, const double* x, double* y) {
   if (!B || !x || !y || x == y) { set_error("bad batch handle or pointers"); return STLS_EINVAL; }
-  hipMemsetAsync(B->S, 0, sizeof(PcgScalars) * B->nprob, B->stream);  // no problem is masked
+  const hipError_t e = hipMemsetAsync(B->S, 0, sizeof(PcgScalars) * B->nprob, B->stream);  // no problem is masked
+  if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
   return bmatvec(B, x, y, nullptr);
 }
 
 int stls_batch_prec_apply(stls_batch_handle B, const double* r, double* s) {
   if (!B || !r || !s || r == s) { set_error("bad batch handle or pointers"); return STLS_EINVAL; }
-  hipMemsetAsync(B->S, 0, sizeof(PcgScalars) * B->nprob, B->stream);
+  const hipError_t e = hipMemsetAsync(B->S, 0, sizeof(PcgScalars) * B->nprob, B->stream);  // no problem is masked
+  if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
   return bprec(B, r, s, nullptr);
 }
 
@@ -1020,7 +1084,7 @@ static int batch_pcg(stls_batch_handle B, const double* b, double* x, double rto
   double* p = B->buf[2];
   double* q = B->buf[3];
   int s = STLS_OK;
-  const int gv = grid_items(B->vec.count);
+  const int gv = grid_items(B->vec.count, B->tune.grid_vec);
   hipLaunchKernelGGL(bvec_kernel, dim3(gv), dim3(kT), 0, st, (int)BV_INIT, x, r, p, q, b, B->desc, B->vec.dev,
                      B->vec.count, B->S, B->partials);
   if ((s = bfin(B, B->vec, BF_BNORM, rtol))) return s;
@@ -1044,29 +1108,40 @@ static int batch_pcg(stls_batch_handle B, const double* b, double* x, double rto
     const hipError_t le = hipGetLastError();
     return le == hipSuccess ? STLS_OK : hip_fail(le, "batched PCG launch");
   };
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // graphs of one iteration and (graph_depth > 1) of graph_depth iterations:
+  // the host reads the scalars once per graph launch, and the one-iteration
+  // graph takes the last iterations before maxit, so no problem runs more
+  // than maxit iterations
+  const int depth = std::max(1, B->tune.graph_depth);
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
   if (B->use_graph) {  // capture failure falls back to direct launches
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-      const int cs = body();
-      if (hipStreamEndCapture(st, &graph) != hipSuccess || cs != STLS_OK ||
-          hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        graph = nullptr;
-        exec = nullptr;
+    for (int g = 0; g < (depth > 1 ? 2 : 1); ++g) {
+      const int reps = g == 0 ? 1 : depth;
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) break;
+      int cs = STLS_OK;
+      for (int r = 0; r < reps && cs == STLS_OK; ++r) cs = body();
+      if (hipStreamEndCapture(st, &graph[g]) != hipSuccess || cs != STLS_OK ||
+          hipGraphInstantiate(&exec[g], graph[g], nullptr, nullptr, 0) != hipSuccess) {
+        if (graph[g]) (void)hipGraphDestroy(graph[g]);
+        graph[g] = nullptr;
+        exec[g] = nullptr;
         (void)hipGetLastError();
+        break;
       }
     }
   }
-  B->graph_used = exec != nullptr;
+  B->graph_used = exec[0] != nullptr;
   int status = STLS_ENOCONV;
-  for (int k = 1; k <= maxit; ++k) {
-    if (exec) {
-      const hipError_t ge = hipGraphLaunch(exec, st);
+  for (int k = 0; k < maxit;) {
+    const bool deep = exec[1] != nullptr && maxit - k >= depth;
+    if (deep || exec[0]) {
+      const hipError_t ge = hipGraphLaunch(deep ? exec[1] : exec[0], st);
       if (ge != hipSuccess) { s = hip_fail(ge, "hipGraphLaunch"); break; }
     } else if ((s = body())) {
       break;
     }
+    k += deep ? depth : 1;
     if ((s = read_scalars(B))) break;
     bool all = true, bad = false;
     for (int i = 0; i < B->nprob; ++i) {
@@ -1075,8 +1150,10 @@ static int batch_pcg(stls_batch_handle B, const double* b, double* x, double rto
     }
     if (all) { status = bad ? STLS_EBREAKDOWN : STLS_OK; break; }
   }
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
+  for (int g = 0; g < 2; ++g) {
+    if (exec[g]) (void)hipGraphExecDestroy(exec[g]);
+    if (graph[g]) (void)hipGraphDestroy(graph[g]);
+  }
   if (s) return s;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "batched PCG launch");
@@ -1091,6 +1168,333 @@ static int batch_pcg(stls_batch_handle B, const double* b, double* x, double rto
   if (nan) { set_error("non-finite value in a batched problem"); return STLS_ENAN; }
   if (status == STLS_ENOCONV) set_error("some batched problems did not reach rtol within maxit");
   return status;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Autotuner of the batched kernels' work-item shapes and launch geometry.
+
+#ifndef STLS_BATCH_SOURCE_HASH
+#define STLS_BATCH_SOURCE_HASH "unhashed"
+#endif
+
+namespace {
+
+const char* const kTuneNames[kTuneFields] = {"vec_chunk",  "inner_steps", "outer_chunk", "grid_fd",
+                                             "grid_inner", "grid_outer",  "grid_vec",    "graph_depth"};
+
+int* tune_field(BatchTuning& T, int f) { return reinterpret_cast<int*>(&T) + f; }
+
+bool tune_valid(const BatchTuning& T) {
+  auto in = [](int v, int lo, int hi) { return v >= lo && v <= hi; };
+  return in(T.vec_chunk, 256, 1 << 20) && T.vec_chunk % 256 == 0 && in(T.inner_steps, 1, 64) &&
+         in(T.outer_chunk, 1, 1 << 16) && in(T.grid_fd, 1, 1 << 16) && in(T.grid_inner, 1, 1 << 16) &&
+         in(T.grid_outer, 1, 1 << 16) && in(T.grid_vec, 1, 1 << 16) && in(T.graph_depth, 1, 64);
+}
+
+// Cache key: the batch kernels' source hash, the device's architecture and a
+// 64-bit FNV-1a hash of the batch's shape (d and every problem's sizes and
+// degree): a cached choice is reused only for the same kernels on the same
+// kind of device and the same problem set.
+std::string tune_key(const stls_batch_ctx* B) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int v) {
+    for (int b = 0; b < 4; ++b) {
+      h ^= (uint64_t)((v >> (8 * b)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  mix(B->d);
+  mix(B->nprob);
+  for (const BProb& P : B->hdesc) {
+    for (int k = 0; k <= B->d; ++k) mix(P.n[k]);
+    mix(P.p[0]);
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  for (char& c : arch)
+    if (c == ':' || c == '"' || c == ' ') c = '_';
+  char buf[32];
+  std::snprintf(buf, sizeof(buf), "%016llx", (unsigned long long)h);
+  return std::string(STLS_BATCH_SOURCE_HASH).substr(0, 16) + "/" + arch + "/" + buf;
+}
+
+// The cache file is a JSON object of objects of integers,
+//   {"<key>": {"vec_chunk": 4096, ...}, ...};
+// the reader accepts exactly that shape (what the writer produces).
+using TuneCache = std::map<std::string, std::map<std::string, long long>>;
+
+bool read_cache(const char* path, TuneCache& out) {
+  std::ifstream f(path);
+  if (!f) return true;  // no file yet: empty cache
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string t = ss.str();
+  size_t i = 0;
+  auto ws = [&]() { while (i < t.size() && std::isspace((unsigned char)t[i])) ++i; };
+  auto str = [&](std::string& v) -> bool {
+    ws();
+    if (i >= t.size() || t[i] != '"') return false;
+    const size_t j = t.find('"', i + 1);
+    if (j == std::string::npos) return false;
+    v = t.substr(i + 1, j - i - 1);
+    i = j + 1;
+    return true;
+  };
+  auto ch = [&](char c) -> bool { ws(); if (i < t.size() && t[i] == c) { ++i; return true; } return false; };
+  if (!ch('{')) return false;
+  if (ch('}')) return true;
+  do {
+    std::string key;
+    if (!str(key) || !ch(':') || !ch('{')) return false;
+    auto& ent = out[key];
+    if (!ch('}')) {
+      do {
+        std::string name;
+        if (!str(name) || !ch(':')) return false;
+        ws();
+        size_t used = 0;
+        long long v = 0;
+        try { v = std::stoll(t.substr(i, 24), &used); } catch (...) { return false; }
+        i += used;
+        ent[name] = v;
+      } while (ch(','));
+      if (!ch('}')) return false;
+    }
+  } while (ch(','));
+  return ch('}');
+}
+
+bool write_cache(const char* path, const TuneCache& c) {
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp);
+    if (!f) return false;
+    f << "{";
+    bool first = true;
+    for (const auto& e : c) {
+      f << (first ? "\n" : ",\n") << " \"" << e.first << "\": {";
+      first = false;
+      bool f2 = true;
+      for (const auto& kv : e.second) {
+        f << (f2 ? "" : ", ") << "\"" << kv.first << "\": " << kv.second;
+        f2 = false;
+      }
+      f << "}";
+    }
+    f << "\n}\n";
+    if (!f) return false;
+  }
+  return std::rename(tmp.c_str(), path) == 0;
+}
+
+// Mean time of `reps` back-to-back runs of `launch` on the batch's stream
+// (after one untimed run), in milliseconds.
+template <class F>
+int time_ms(stls_batch_ctx* B, F&& launch, int reps, float* ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventCreate");
+  int st = launch();
+  if (!st && hipEventRecord(a, B->stream) != hipSuccess) st = STLS_EHIP;
+  for (int r = 0; r < reps && !st; ++r) st = launch();
+  if (!st && hipEventRecord(b, B->stream) != hipSuccess) st = STLS_EHIP;
+  if (!st && hipEventSynchronize(b) != hipSuccess) st = STLS_EHIP;
+  float t = 0.f;
+  if (!st && hipEventElapsedTime(&t, a, b) != hipSuccess) st = STLS_EHIP;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (st) return st == STLS_EHIP ? hip_fail(hipGetLastError(), "autotune timing") : st;
+  *ms = t / reps;
+  return STLS_OK;
+}
+
+// Best of three timings (the minimum rejects interference).
+template <class F>
+int best_of(stls_batch_ctx* B, F&& launch, int reps, float* ms) {
+  float best = 1e30f;
+  for (int k = 0; k < 3; ++k) {
+    float t;
+    const int st = time_ms(B, launch, reps, &t);
+    if (st) return st;
+    best = std::min(best, t);
+  }
+  *ms = best;
+  return STLS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stls_batch_get_tuning(stls_batch_handle B, int* vals) {
+  if (!B || !vals) { set_error("NULL batch or values"); return STLS_EINVAL; }
+  for (int f = 0; f < kTuneFields; ++f) vals[f] = *tune_field(B->tune, f);
+  return STLS_OK;
+}
+
+int stls_batch_set_tuning(stls_batch_handle B, const int* vals) {
+  if (!B || !vals) { set_error("NULL batch or values"); return STLS_EINVAL; }
+  BatchTuning T;
+  for (int f = 0; f < kTuneFields; ++f) *tune_field(T, f) = vals[f];
+  if (!tune_valid(T)) { set_error("batch tuning value out of range"); return STLS_EINVAL; }
+  if (hipStreamSynchronize(B->stream) != hipSuccess || hipStreamSynchronize(B->solve_stream) != hipSuccess)
+    return hip_fail(hipGetLastError(), "hipStreamSynchronize");
+  B->tune = T;
+  return build_tuned_lists(B);
+}
+
+int stls_batch_autotune(stls_batch_handle B, const char* cache_path, int* measured) {
+  if (!B) { set_error("NULL batch"); return STLS_EINVAL; }
+  if (measured) *measured = 0;
+  const std::string key = tune_key(B);
+  TuneCache cache;
+  if (cache_path && !read_cache(cache_path, cache)) {
+    set_error(std::string("autotune cache is not in the expected format: ") + cache_path);
+    return STLS_EINVAL;
+  }
+  if (cache_path && cache.count(key)) {  // reuse the stored choice
+    BatchTuning T = B->tune;
+    for (int f = 0; f < kTuneFields; ++f) {
+      auto it = cache[key].find(kTuneNames[f]);
+      if (it != cache[key].end()) *tune_field(T, f) = (int)it->second;
+    }
+    if (tune_valid(T)) {
+      int v[kTuneFields];
+      for (int f = 0; f < kTuneFields; ++f) v[f] = *tune_field(T, f);
+      return stls_batch_set_tuning(B, v);
+    }
+  }
+  if (hipStreamSynchronize(B->stream) != hipSuccess) return hip_fail(hipGetLastError(), "hipStreamSynchronize");
+  // the measurements run on the batch's own (capturable) stream; the caller's
+  // stream is idle meanwhile and is restored on every return path
+  hipStream_t caller = B->stream;
+  B->stream = B->solve_stream;
+  struct Restore {
+    stls_batch_ctx* B;
+    hipStream_t s;
+    ~Restore() {
+      (void)hipStreamSynchronize(B->solve_stream);
+      B->stream = s;
+    }
+  } restore{B, caller};
+  // every problem active (done = flag = 0) so that no kernel skips its items;
+  // operands are the batch's work vectors (their values do not change the
+  // kernels' work)
+  hipStream_t st = B->stream;
+  if (hipMemsetAsync(B->S, 0, sizeof(PcgScalars) * B->nprob, st) != hipSuccess)
+    return hip_fail(hipGetLastError(), "hipMemsetAsync");
+  for (int i = 0; i < 4; ++i)
+    if (hipMemsetAsync(B->buf[i], 0, sizeof(double) * B->total, st) != hipSuccess)
+      return hip_fail(hipGetLastError(), "hipMemsetAsync");
+  int rc = STLS_OK;
+  auto apply = [&](const BatchTuning& T) -> int {
+    int v[kTuneFields];
+    for (int f = 0; f < kTuneFields; ++f) v[f] = *tune_field(const_cast<BatchTuning&>(T), f);
+    return stls_batch_set_tuning(B, v);
+  };
+  // one knob group at a time, the others held at their current values
+  struct Group {
+    std::vector<int> fields;
+    std::vector<std::vector<int>> cands;
+    std::function<int()> stage;
+  };
+  auto vec_stage = [&]() -> int {
+    hipLaunchKernelGGL(bvec_kernel, dim3(grid_items(B->vec.count, B->tune.grid_vec)), dim3(kT), 0, st, (int)BV_XR,
+                       B->buf[4], B->buf[5], B->buf[2], B->buf[3], B->buf[0], B->desc, B->vec.dev, B->vec.count, B->S,
+                       B->partials);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? STLS_OK : hip_fail(e, "bvec_kernel launch");
+  };
+  auto mv_stage = [&]() -> int { return bmatvec(B, B->buf[2], B->buf[3], B->buf[2]); };
+  auto fd_stage = [&]() -> int { return bprec(B, B->buf[0], B->buf[1], B->buf[0]); };
+  std::vector<Group> groups;
+  {
+    Group g{{0, 6}, {}, vec_stage};
+    for (int c : {1024, 2048, 4096, 8192, 16384})
+      for (int gr : {1024, 2048, 4096}) g.cands.push_back({c, gr});
+    groups.push_back(g);
+  }
+  if (B->d == 2) {
+    Group g{{1, 4}, {}, mv_stage};
+    for (int c : {2, 4, 8, 16})
+      for (int gr : {1024, 2048, 4096}) g.cands.push_back({c, gr});
+    groups.push_back(g);
+  }
+  {
+    Group g{{2, 5}, {}, mv_stage};
+    for (int c : {8, 16, 32, 64, 128})
+      for (int gr : {1024, 2048, 4096}) g.cands.push_back({c, gr});
+    groups.push_back(g);
+  }
+  {
+    Group g{{3}, {}, fd_stage};
+    for (int gr : {512, 1024, 2048, 4096, 8192}) g.cands.push_back({gr});
+    groups.push_back(g);
+  }
+  for (Group& g : groups) {
+    BatchTuning best = B->tune;
+    float best_ms = 1e30f;
+    for (const auto& cand : g.cands) {
+      BatchTuning T = B->tune;
+      for (size_t j = 0; j < g.fields.size(); ++j) *tune_field(T, g.fields[j]) = cand[j];
+      if ((rc = apply(T))) return rc;
+      float ms = 0.f;
+      if ((rc = best_of(B, g.stage, 3, &ms))) return rc;
+      if (ms < best_ms) { best_ms = ms; best = T; }
+    }
+    if ((rc = apply(best))) return rc;
+  }
+  // PCG iterations per graph launch: whole solves of a right-hand side of
+  // ones on scratch vectors
+  double *tb = nullptr, *tx = nullptr;
+  if (hipMalloc((void**)&tb, sizeof(double) * B->total) != hipSuccess ||
+      hipMalloc((void**)&tx, sizeof(double) * B->total) != hipSuccess) {
+    if (tb) (void)hipFree(tb);
+    set_error("hipMalloc (autotune vectors)");
+    return STLS_ENOMEM;
+  }
+  {
+    std::vector<double> ones((size_t)B->total, 1.0);
+    if (hipMemcpy(tb, ones.data(), sizeof(double) * B->total, hipMemcpyHostToDevice) != hipSuccess)
+      rc = hip_fail(hipGetLastError(), "hipMemcpy");
+  }
+  if (!rc) {
+    BatchTuning best = B->tune;
+    float best_ms = 1e30f;
+    const bool graph_on = B->use_graph;
+    B->use_graph = true;
+    for (int depth : {1, 2, 4, 8}) {
+      BatchTuning T = B->tune;
+      T.graph_depth = depth;
+      if ((rc = apply(T))) break;
+      float ms = 0.f;
+      auto solve = [&]() -> int {
+        const int r = batch_pcg(B, tb, tx, 1e-8, 500, nullptr, nullptr);
+        return (r == STLS_OK || r == STLS_ENOCONV) ? STLS_OK : r;
+      };
+      if ((rc = best_of(B, solve, 1, &ms))) break;
+      if (ms < best_ms) { best_ms = ms; best = T; }
+    }
+    B->use_graph = graph_on;
+    if (!rc) rc = apply(best);
+  }
+  (void)hipFree(tb);
+  (void)hipFree(tx);
+  if (rc) return rc;
+  if (measured) *measured = 1;
+  if (cache_path) {
+    auto& ent = cache[key];
+    ent.clear();
+    for (int f = 0; f < kTuneFields; ++f) ent[kTuneNames[f]] = *tune_field(B->tune, f);
+    if (!write_cache(cache_path, cache)) {
+      set_error(std::string("cannot write the autotune cache ") + cache_path);
+      return STLS_EINVAL;
+    }
+  }
+  return STLS_OK;
 }
 
 int stls_batch_pcg_solve(stls_batch_handle B, const double* b, double* x, double rtol, int maxit, int* iters,
