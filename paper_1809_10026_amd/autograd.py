@@ -4,8 +4,8 @@ HeatSolve maps (f, kappa) to u = A_kappa^{-1} B_kappa f with the library's
 FD-preconditioned PCG; its backward pass solves the adjoint system with the
 same solver (A_kappa is symmetric) and applies B_kappa^T and the kappa
 derivative.  Only the forward solution u is kept for the backward pass (no
-PCG iterates are stored).  Misfit maps u to (u - u*)^T M_Q (u - u*).
-Tensors are float64 CUDA vectors in colexicographic order; kappa is a
+PCG iterates are stored).  Misfit maps u to (u - u*)^T M_Q (u - u*); the
+library returns its gradient 2 M_Q (u - u*) with the loss.  Tensors are float64 CUDA vectors in colexicographic order; kappa is a
 0-dim float64 tensor.  Every operator runs in the HIP library; torch only
 scales the incoming gradient.
 """
@@ -47,7 +47,7 @@ class Misfit(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         (q,) = ctx.saved_tensors
-        return 2.0 * g * q, None, None
+        return g * q, None, None
 
 
 def heat_solve(f, kappa, solver, rtol=1e-10, maxit=1000):

@@ -593,8 +593,15 @@ int stls_misfit(stls_handle h, const double* u, const double* ustar, double* q, 
   hipLaunchKernelGGL(sub_kernel, dim3(grid_for(h->ndof)), dim3(kT), 0, h->stream, u, ustar, e, (long long)h->ndof);
   hipError_t er = hipGetLastError();
   if (er != hipSuccess) return hip_fail(er, "sub_kernel launch");
-  if ((st = stls_mass_apply(h, e, q))) return st;
-  return device_dot(h, e, q, h->ndof, loss);
+  // q = 2 M_Q e: the factor 2 in the last mode product is an exact scaling,
+  // so e . q / 2 is the loss e^T M_Q e bit for bit
+  std::vector<Fac> f;
+  for (int k = 0; k <= h->d; ++k) f.push_back(sq(h->dd[k], h->dd[k].M));
+  if ((st = apply_chain(h, e, q, f, 2.0, false, h->ftmp[0], h->ftmp[1]))) return st;
+  double two_loss = 0.0;
+  if ((st = device_dot(h, e, q, h->ndof, &two_loss))) return st;
+  *loss = 0.5 * two_loss;
+  return STLS_OK;
 }
 
 }  // extern "C"
