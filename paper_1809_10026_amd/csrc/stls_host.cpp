@@ -393,6 +393,8 @@ int upload_fd_operands(stls_ctx* h, int k) {
   std::vector<float> af32(af.begin(), af.end()), ab32(ab.begin(), ab.end());
   std::vector<uint16_t> hf((size_t)np * kp, 0), lf((size_t)np * kp, 0), hb((size_t)np * kp, 0),
       lb((size_t)np * kp, 0);
+  std::vector<float> rf32((size_t)np * kp, 0.f), rb32((size_t)np * kp, 0.f);
+  std::vector<double> rf64((size_t)np * kp, 0.0), rb64((size_t)np * kp, 0.0);
   for (int i = 0; i < n; ++i)
     for (int kk = 0; kk < n; ++kk) {
       const float wf = (float)U(kk, i), wb = (float)U(i, kk);
@@ -401,6 +403,10 @@ int upload_fd_operands(stls_ctx* h, int k) {
       lf[(size_t)i * kp + kk] = to_bf16(wf - from_bf16(h1));
       hb[(size_t)i * kp + kk] = h2;
       lb[(size_t)i * kp + kk] = to_bf16(wb - from_bf16(h2));
+      rf32[(size_t)i * kp + kk] = wf;
+      rb32[(size_t)i * kp + kk] = wb;
+      rf64[(size_t)i * kp + kk] = U(kk, i);
+      rb64[(size_t)i * kp + kk] = U(i, kk);
     }
   int st;
   if ((st = dev_upload(&dd.Afwd64, af.data(), af.size(), h->stream))) return st;
@@ -411,6 +417,10 @@ int upload_fd_operands(stls_ctx* h, int k) {
   if ((st = dev_upload(&dd.Lfwd, lf.data(), lf.size(), h->stream))) return st;
   if ((st = dev_upload(&dd.Hbwd, hb.data(), hb.size(), h->stream))) return st;
   if ((st = dev_upload(&dd.Lbwd, lb.data(), lb.size(), h->stream))) return st;
+  if ((st = dev_upload(&dd.Rfwd32, rf32.data(), rf32.size(), h->stream))) return st;
+  if ((st = dev_upload(&dd.Rbwd32, rb32.data(), rb32.size(), h->stream))) return st;
+  if ((st = dev_upload(&dd.Rfwd64, rf64.data(), rf64.size(), h->stream))) return st;
+  if ((st = dev_upload(&dd.Rbwd64, rb64.data(), rb64.size(), h->stream))) return st;
   return STLS_OK;
 }
 
@@ -522,8 +532,10 @@ static void free_ctx(stls_ctx* h) {
   if (!h) return;
   for (int k = 0; k <= kMaxDim; ++k) {
     DevDir& dd = h->dd[k];
-    void* ptrs[] = {dd.M, dd.K, dd.J, dd.Afwd64, dd.Abwd64, dd.Afwd32, dd.Abwd32, dd.Hfwd, dd.Lfwd,
-                    dd.Hbwd, dd.Lbwd, dd.lam, dd.Mbar, dd.Cbar, dd.Gbar, dd.Kbar, dd.Jbar, dd.Hbar, dd.Dbar};
+    void* ptrs[] = {dd.M,      dd.K,      dd.J,      dd.Afwd64, dd.Abwd64, dd.Afwd32, dd.Abwd32,
+                    dd.Hfwd,   dd.Lfwd,   dd.Hbwd,   dd.Lbwd,   dd.Rfwd32, dd.Rbwd32, dd.Rfwd64,
+                    dd.Rbwd64, dd.lam,    dd.Mbar,   dd.Cbar,   dd.Gbar,   dd.Kbar,   dd.Jbar,
+                    dd.Hbar,   dd.Dbar};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
   }

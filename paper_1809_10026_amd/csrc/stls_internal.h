@@ -48,6 +48,10 @@ struct DevDir {
   uint16_t* Lfwd = nullptr;
   uint16_t* Hbwd = nullptr;
   uint16_t* Lbwd = nullptr;
+  float* Rfwd32 = nullptr;     // W row-major [i*kpad + k] in FP32 and FP64 (five-pass FD)
+  float* Rbwd32 = nullptr;
+  double* Rfwd64 = nullptr;
+  double* Rbwd64 = nullptr;
   int kpad = 0;
   double* lam = nullptr;
   int m = 0;                   // full space size (forcing coefficients)
@@ -180,10 +184,10 @@ int pcg_run(stls_ctx* h, const double* b, double* x, double rtol, int maxit, int
             double* relres);
 int upload_fd_operands(stls_ctx* h, int k);
 DiagScale diag_scale_args(const stls_ctx* h);
-// Five-pass BF16x3 FD chain for d = 3 (stls_fd.hip).
-bool fd_bf16_five_pass_covers(const stls_ctx* h);
-int prec_apply_bf16x3_five_pass(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
-                                int* nparts, bool scale);
+// Five-pass FD chain for d = 3 in the handle's FD precision (stls_fd.hip).
+bool fd_five_pass_covers(const stls_ctx* h);
+int prec_apply_five_pass(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
+                         int* nparts, bool scale);
 int upload_diff_bands(stls_ctx* h);
 int ensure_diff_operands(stls_ctx* h);
 // Device address of the static workspace of the allocation-free entry points

@@ -725,8 +725,8 @@ static int prec_apply_plain(stls_ctx* h, const double* r, double* s, const doubl
 
 int launch_prec_apply(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
                       int* nparts) {
-  if (h->fd_mode == STLS_FD_BF16X3 && fd_bf16_five_pass_covers(h))
-    return prec_apply_bf16x3_five_pass(h, r, s, dot_with, partials, nparts, h->fd_scale);  // scaling fused
+  if (fd_five_pass_covers(h))
+    return prec_apply_five_pass(h, r, s, dot_with, partials, nparts, h->fd_scale);  // scaling fused
   if (!h->fd_scale) return prec_apply_plain(h, r, s, dot_with, partials, nparts);
   // scaled: sigma o r into a matvec intermediate (free while the FD runs),
   // the chain, then sigma o s in place with the dot product

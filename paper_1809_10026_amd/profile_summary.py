@@ -30,8 +30,8 @@ CALIB_MATCH = "MulFunctor"  # torch's elementwise multiply kernel (the calibrati
 CLASSES = [
     ("mv_outer_dma_kernel", "mv_outer"), ("mv_outer_kernel", "mv_outer"),
     ("mv_inner_slab_kernel", "mv_inner2"), ("mv_inner12_kernel", "mv_inner2"), ("mv_inner1_kernel", "mv_inner1"),
-    ("fd_slab_bf16_kernel", "fd_slab"),
-    ("fd_strided_bf16_kernel", None),  # fd_space or fd_time by the FUSED argument
+    ("fd_slab_kernel", "fd_slab"),
+    ("fd_strided_kernel", None),  # fd_space or fd_time by the FUSED argument
     ("fd_mode_bf16x3_kernel", None), ("fd_mode_kernel", None),
     ("update_xr_kernel", "vec"), ("update_p_kernel", "vec"), ("dot_kernel", "vec"),
     ("finalize_kernel", "reduce"),
@@ -49,7 +49,7 @@ def source_hash() -> str:
 
 
 # position of the FUSED template argument (time kernel) in the FD kernels' argument lists
-FUSED_ARG = {"fd_strided_bf16_kernel": 1, "fd_mode_bf16x3_kernel": 4, "fd_mode_kernel": 6}
+FUSED_ARG = {"fd_strided_kernel": 2, "fd_mode_bf16x3_kernel": 4, "fd_mode_kernel": 6}
 
 
 def _mangled_template_args(name: str, frag: str):
