@@ -22,8 +22,11 @@ Modules
   pcg       preconditioned conjugate gradient (§4.2, §5)
   grad      adjoint gradients of a space-time misfit (extension, see module)
   norms     error norms of the manufactured-solution study (§5.1)
+  geometry  mapped domains: pulled-back spatial matrices, the geometry
+            coefficients, Algorithm 2 and the preconditioner P^G (§4.4,
+            Appendix A.3), loads and error norms on the mapped domain
 
 Parity status: every function is pinned by a test in tests/test_oracle_*.py
 except where its docstring says "parity unpinned".
 """
-from . import bspline, assemble, system, fd, pcg, norms  # noqa: F401
+from . import bspline, assemble, system, fd, pcg, norms, geometry  # noqa: F401
