@@ -275,6 +275,7 @@ def main():
     err_norms = gpu_error_norms(stls, torch)
     batch = gpu_batch(stls, torch)
     lifting = gpu_lifting(stls, torch, knots, degs)
+    geometry = gpu_geometry(stls, torch)
 
     cpu = None
     err_vs_oracle = None
@@ -321,6 +322,7 @@ def main():
         "error_norms": err_norms,
         "batch": batch,
         "lifting": lifting,
+        "mapped_domain": geometry,
         "setup_s": setup_s,
         "roofline": roofline,
         "roofline_note": "kernel durations from HIP events recorded around every launch on the solver's "
@@ -410,6 +412,39 @@ def gpu_batch(stls, torch, steps=3):
             "max_relres": float(max(rels)),
             "autotune": {"seconds": tune_s, "tuning": B.tuning, "default_tuning": default_tuning,
                          "default_seconds": dt_default}}
+
+
+def gpu_geometry(stls, torch, n_sub=16, p=2, reps=3):
+    """Mapped domain (§4.4, §5.2 Table 2): the rotated quarter annulus,
+    n_sub = 16, p_s = p_t = 2 (ndof 16^3 x 17 = 69,632), right-hand side
+    U[-1, 1] (seed 1), PCG to 1e-8 with the parametric P and with the
+    geometry-aware P^G (FP64 FD; P^G also with bf16x3 FD).  Host setup
+    (stencil assembly, Algorithm 2, eigendecompositions) timed apart."""
+    from stls_inputs import problem_knots, uniform_pm1
+    knots, degs = problem_knots(3, n_sub, p)
+    out = {"workload": f"rotated quarter annulus, n_sub={n_sub}, p={p}, RHS U[-1,1] seed 1, rtol 1e-8",
+           "table2_paper_iterations": {"P": 126, "P^G": 35}}
+    for name, prec, mode in (("P", stls.STLS_PREC_PARAMETRIC, stls.STLS_FD_FP64),
+                             ("P^G", stls.STLS_PREC_GEOMETRY, stls.STLS_FD_FP64),
+                             ("P^G bf16x3", stls.STLS_PREC_GEOMETRY, stls.STLS_FD_BF16X3)):
+        t = time.perf_counter()
+        S = stls.Solver(knots, degs, geometry=stls.STLS_GEOM_ROTATED_QUARTER_ANNULUS, prec=prec)
+        setup_s = time.perf_counter() - t
+        S.set_fd_precision(mode)
+        b = torch.as_tensor(uniform_pm1(S.ndof, 1)).cuda()
+        x = torch.empty_like(b)
+        S.solve(b, 1e-8, 3000, out=x)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            _, it, rel = S.solve(b, 1e-8, 3000, out=x)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / reps
+        out[name] = {"ndof": S.ndof, "iters": it, "relres": rel, "seconds": dt, "setup_s": setup_s,
+                     "dof_per_s": S.ndof / dt}
+        log(f"mapped domain {name}: {it} iterations, {dt*1e3:.2f} ms, setup {setup_s:.2f} s")
+        S.close()
+    return out
 
 
 def gpu_lifting(stls, torch, knots, degs, reps=20):

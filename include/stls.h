@@ -78,6 +78,46 @@ typedef enum stls_fd_precision {
 int stls_setup(int d, const int* nknots, const double* const* knots, const int* degree,
                double kappa, void* stream, stls_handle* out);
 
+/* ------------------------------------------------------------------------
+ * Mapped spatial domains (§2.2 isoparametric spaces, §4.4, §5.1-5.2).
+ * Omega = G((0,1)^d) for one of the paper's domains; trial and test
+ * functions are the restricted tensor B-splines composed with G^{-1}.  The
+ * system keeps the time Kronecker structure of §4.1 with sparse spatial
+ * factors M_s = int B_i B_j, L_s = int grad B_i . grad B_j and
+ * J_s = int Lap B_i Lap B_j over Omega, assembled on the host by Gauss
+ * quadrature with p + 3 points per non-empty span and applied as stencils.
+ * ------------------------------------------------------------------------ */
+typedef enum stls_geometry {
+  STLS_GEOM_UNIT_BOX = 0,                /* (0,1)^d: stls_setup */
+  STLS_GEOM_QUARTER_ANNULUS = 1,         /* d = 2: 1 < r < 2, 0 < theta < pi/2 (§5.1);
+                                            x = r cos(theta), y = r sin(theta),
+                                            r = 1 + eta_1, theta = (pi/2) eta_2 */
+  STLS_GEOM_ROTATED_QUARTER_ANNULUS = 2  /* d = 3: that quarter annulus revolved by pi/2
+                                            about the line y = -1, z = 0 (§5.2):
+                                            x = x0, y = -1 + (y0 + 1) cos(phi),
+                                            z = (y0 + 1) sin(phi), phi = (pi/2) eta_3 */
+} stls_geometry;
+
+typedef enum stls_mapped_prec {
+  STLS_PREC_PARAMETRIC = 0,  /* P of §4.2 from the parametric factors (G ignored) */
+  STLS_PREC_GEOMETRY = 1     /* P^G = D^1/2 Pbar^G D^1/2 (§4.4): factors weighted by the
+                                separable approximation (Algorithm 2 of Appendix A.3,
+                                maxit = 2) of the geometry coefficients c_k at the element
+                                barycentres, D = diag(A) / diag(Pbar^G) */
+} stls_mapped_prec;
+
+/*
+ * stls_setup on a mapped domain.  Arguments as stls_setup, plus geometry
+ * (stls_geometry; d must match) and prec (stls_mapped_prec).  stls_matvec,
+ * stls_prec_apply (every FD precision), stls_pcg_solve, stls_set_kappa and
+ * the profiling calls work as on the unit box; stls_set_fd_scaling(h, 1)
+ * and the differentiation, lifting and error-norm calls return STLS_EINVAL.
+ * Host work: the stencils cost O(ns (p+1)^(2d) (p+3)^d) and need at most
+ * 2^26 quadrature points; synchronises the stream.  Errors as stls_setup.
+ */
+int stls_setup_mapped(int d, const int* nknots, const double* const* knots, const int* degree, double kappa,
+                      int geometry, int prec, void* stream, stls_handle* out);
+
 /* Release every device and host resource of the handle (NULL is a no-op). */
 int stls_destroy(stls_handle h);
 

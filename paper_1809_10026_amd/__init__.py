@@ -40,6 +40,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 STLS_OK, STLS_EINVAL, STLS_ENOMEM, STLS_EHIP, STLS_ENOCONV, STLS_ENAN, STLS_EBREAKDOWN = 0, -1, -2, -3, -4, -5, -6
 STLS_FD_FP64, STLS_FD_FP32, STLS_FD_BF16X3 = 0, 1, 2
+STLS_GEOM_UNIT_BOX, STLS_GEOM_QUARTER_ANNULUS, STLS_GEOM_ROTATED_QUARTER_ANNULUS = 0, 1, 2
+STLS_PREC_PARAMETRIC, STLS_PREC_GEOMETRY = 0, 1
 # batch tuning fields, in the order of enum stls_batch_tune_field
 TUNE_FIELDS = ("vec_chunk", "inner_steps", "outer_chunk", "grid_fd", "grid_inner", "grid_outer", "grid_vec",
                "graph_depth")
@@ -49,6 +51,9 @@ _c_dbl_p = ctypes.c_void_p
 _sig = {
     "stls_setup": (ctypes.c_int, [ctypes.c_int, _c_int_p, ctypes.POINTER(ctypes.c_void_p), _c_int_p,
                                   ctypes.c_double, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "stls_setup_mapped": (ctypes.c_int, [ctypes.c_int, _c_int_p, ctypes.POINTER(ctypes.c_void_p), _c_int_p,
+                                         ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
     "stls_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "stls_get_shape": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, ctypes.POINTER(ctypes.c_int64)]),
     "stls_get_factor": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
@@ -137,15 +142,21 @@ def _dev_ptr(t, n, name):
 # ---------------------------------------------------------------------------
 # C ABI mirrors (same names); handles are opaque ctypes.c_void_p values.
 
-def stls_setup(knots, degrees, kappa=1.0, stream=None):
-    """Handle for one problem; knots: d+1 host arrays (time last)."""
+def stls_setup(knots, degrees, kappa=1.0, stream=None, geometry=0, prec=0):
+    """Handle for one problem; knots: d+1 host arrays (time last).  geometry
+    (STLS_GEOM_*) != 0 sets up a mapped domain with preconditioner prec
+    (STLS_PREC_PARAMETRIC or STLS_PREC_GEOMETRY)."""
     d = len(knots) - 1
     arrs = [np.ascontiguousarray(k, dtype=np.float64) for k in knots]
     nk = (ctypes.c_int * (d + 1))(*[len(a) for a in arrs])
     ptrs = (ctypes.c_void_p * (d + 1))(*[a.ctypes.data for a in arrs])
     degs = (ctypes.c_int * (d + 1))(*[int(p) for p in degrees])
     h = ctypes.c_void_p()
-    _check(_lib.stls_setup(d, nk, ptrs, degs, float(kappa), _stream_ptr(stream), ctypes.byref(h)), "stls_setup")
+    if geometry:
+        _check(_lib.stls_setup_mapped(d, nk, ptrs, degs, float(kappa), int(geometry), int(prec), _stream_ptr(stream),
+                                      ctypes.byref(h)), "stls_setup_mapped")
+    else:
+        _check(_lib.stls_setup(d, nk, ptrs, degs, float(kappa), _stream_ptr(stream), ctypes.byref(h)), "stls_setup")
     return h
 
 
@@ -422,15 +433,19 @@ class Batch:
 
 # ---------------------------------------------------------------------------
 class Solver:
-    """One space-time heat problem on the unit box; owns a library handle.
+    """One space-time heat problem on the unit box (or, with ``geometry``, on
+    a mapped domain: STLS_GEOM_QUARTER_ANNULUS, d = 2, or
+    STLS_GEOM_ROTATED_QUARTER_ANNULUS, d = 3, with preconditioner ``prec``
+    STLS_PREC_PARAMETRIC or STLS_PREC_GEOMETRY); owns a library handle.
 
     knots/degrees: d+1 entries (space directions, then time).  Vectors are
     float64 CUDA tensors of ``ndof`` entries in colexicographic order.
     """
 
-    def __init__(self, knots, degrees, kappa=1.0, stream=None):
+    def __init__(self, knots, degrees, kappa=1.0, stream=None, geometry=0, prec=0):
         self.d = len(knots) - 1
-        self._h = stls_setup(knots, degrees, kappa, stream)
+        self.geometry = int(geometry)
+        self._h = stls_setup(knots, degrees, kappa, stream, geometry, prec)
         self.shape, self.ndof = stls_get_shape(self._h, self.d)
         self.kappa = float(kappa)
 

@@ -15,7 +15,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstls.so")
-SOURCES = ["stls_host.cpp", "stls_kernels.hip", "stls_fd.hip", "stls_diff.hip", "stls_batch.hip", "stls_norms.hip"]
+SOURCES = ["stls_host.cpp", "stls_geometry.cpp", "stls_kernels.hip", "stls_fd.hip", "stls_diff.hip", "stls_batch.hip",
+           "stls_norms.hip", "stls_mapped.hip"]
 
 # Packed FP32 instructions are kept off on purpose: the compiler would emit
 # them from ordinary float code otherwise.

@@ -333,6 +333,7 @@ int stls_get_forcing_shape(stls_handle h, int* m, int64_t* nfull) {
 }
 
 int stls_load_apply(stls_handle h, const double* f, double* F) {
+  if (h && h->geometry) { set_error("stls_load_apply: unit box only (not available on a mapped domain)"); return STLS_EINVAL; }
   if (!h || !f || !F) { set_error("bad handle or pointers"); return STLS_EINVAL; }
   int st = ensure_diff_operands(h);
   if (st) return st;
@@ -349,6 +350,7 @@ int stls_load_apply(stls_handle h, const double* f, double* F) {
 // allocation (host or device).  Each mode product overwrites its whole
 // output, so nothing in the workspace has to start at zero.
 int stls_load_apply_noalloc(stls_handle h, const double* f, double* F) {
+  if (h && h->geometry) { set_error("stls_load_apply_noalloc: unit box only (not available on a mapped domain)"); return STLS_EINVAL; }
   if (!h || !f || !F) { set_error("bad handle or pointers"); return STLS_EINVAL; }
   if (!h->bands_ready || !h->noalloc_scratch) {
     set_error("handle has no device bands or workspace address (stls_setup did not complete)");
@@ -406,6 +408,7 @@ int stls_load_apply_noalloc(stls_handle h, const double* f, double* F) {
 }
 
 int stls_lift_initial(stls_handle h, const double* u0, double* F) {
+  if (h && h->geometry) { set_error("stls_lift_initial: unit box only (not available on a mapped domain)"); return STLS_EINVAL; }
   if (!h || !u0 || !F) { set_error("bad handle or pointers"); return STLS_EINVAL; }
   int st = ensure_diff_operands(h);
   if (st) return st;
@@ -415,6 +418,7 @@ int stls_lift_initial(stls_handle h, const double* u0, double* F) {
 }
 
 int stls_lift_combine(stls_handle h, const double* u0, const double* x, double* u) {
+  if (h && h->geometry) { set_error("stls_lift_combine: unit box only (not available on a mapped domain)"); return STLS_EINVAL; }
   if (!h || !u0 || !x || !u) { set_error("bad handle or pointers"); return STLS_EINVAL; }
   hipError_t e = hipMemcpyAsync(u, u0, sizeof(double) * (size_t)h->ns, hipMemcpyDeviceToDevice, h->stream);
   if (e == hipSuccess)
@@ -429,6 +433,7 @@ int stls_lift_combine(stls_handle h, const double* u0, const double* x, double* 
 // takes one time product into F.  (16 chains of 4 products at d = 3 become
 // 33 products.)
 int stls_lift_apply(stls_handle h, const double* ub, double* F) {
+  if (h && h->geometry) { set_error("stls_lift_apply: unit box only (not available on a mapped domain)"); return STLS_EINVAL; }
   if (!h || !ub || !F) { set_error("bad handle or pointers"); return STLS_EINVAL; }
   int st = ensure_diff_operands(h);
   if (st) return st;
@@ -498,6 +503,7 @@ int stls_lift_apply(stls_handle h, const double* ub, double* F) {
 }
 
 int stls_lift_embed(stls_handle h, const double* ub, const double* w, double* u) {
+  if (h && h->geometry) { set_error("stls_lift_embed: unit box only (not available on a mapped domain)"); return STLS_EINVAL; }
   if (!h || !ub || !w || !u) { set_error("bad handle or pointers"); return STLS_EINVAL; }
   int st = ensure_diff_operands(h);
   if (st) return st;
@@ -516,6 +522,7 @@ int stls_lift_embed(stls_handle h, const double* ub, const double* w, double* u)
 }
 
 int stls_load_apply_T(stls_handle h, const double* lam, double* gf) {
+  if (h && h->geometry) { set_error("stls_load_apply_T: unit box only (not available on a mapped domain)"); return STLS_EINVAL; }
   if (!h || !lam || !gf) { set_error("bad handle or pointers"); return STLS_EINVAL; }
   int st = ensure_diff_operands(h);
   if (st) return st;
@@ -528,6 +535,7 @@ int stls_load_apply_T(stls_handle h, const double* lam, double* gf) {
 }
 
 int stls_mass_apply(stls_handle h, const double* x, double* y) {
+  if (h && h->geometry) { set_error("stls_mass_apply: unit box only (not available on a mapped domain)"); return STLS_EINVAL; }
   if (!h || !x || !y || x == y) { set_error("bad handle or pointers (x and y must differ)"); return STLS_EINVAL; }
   int st = ensure_diff_operands(h);
   if (st) return st;
@@ -542,6 +550,7 @@ int stls_dot(stls_handle h, const double* a, const double* b, int64_t n, double*
 }
 
 int stls_dkappa(stls_handle h, const double* f, const double* u, const double* lam, double* dk) {
+  if (h && h->geometry) { set_error("stls_dkappa: unit box only (not available on a mapped domain)"); return STLS_EINVAL; }
   if (!h || !f || !u || !lam || !dk) { set_error("bad handle or pointers"); return STLS_EINVAL; }
   int st = ensure_diff_operands(h);
   if (st) return st;
@@ -586,6 +595,7 @@ int stls_dkappa_terms(stls_handle h, const double* f, const double* u, const dou
 }
 
 int stls_misfit(stls_handle h, const double* u, const double* ustar, double* q, double* loss) {
+  if (h && h->geometry) { set_error("stls_misfit: unit box only (not available on a mapped domain)"); return STLS_EINVAL; }
   if (!h || !u || !ustar || !q || !loss) { set_error("bad handle or pointers"); return STLS_EINVAL; }
   int st = ensure_diff_operands(h);
   if (st) return st;

@@ -541,7 +541,8 @@ static void free_ctx(stls_ctx* h) {
   }
   void* ptrs[] = {h->diag64, h->diag32, h->lam_s, h->lam_s_raw, h->work[0], h->work[1], h->work[2], h->work[3], h->work[4],
                   h->work[5], h->fdbuf[0], h->fdbuf[1], h->r, h->z, h->pvec, h->q, h->partials, h->scal,
-                  h->dres, h->ftmp[0], h->ftmp[1], h->lgrp[0], h->lgrp[1], h->lgrp[2], h->lgrp[3]};
+                  h->dres, h->ftmp[0], h->ftmp[1], h->lgrp[0], h->lgrp[1], h->lgrp[2], h->lgrp[3],
+                  h->sten[0], h->sten[1], h->sten[2], h->sigma};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->scal_host) (void)hipHostFree(h->scal_host);
@@ -597,8 +598,8 @@ using namespace stls;
 
 extern "C" {
 
-int stls_setup(int d, const int* nknots, const double* const* knots, const int* degree, double kappa,
-               void* stream, stls_handle* out) {
+static int setup_common(int d, const int* nknots, const double* const* knots, const int* degree, double kappa,
+                        void* stream, int geometry, int prec, stls_handle* out) {
   if (!out) { set_error("out is NULL"); return STLS_EINVAL; }
   *out = nullptr;
   if (d < 1 || d > kMaxDim) { set_error("d must be 1, 2 or 3"); return STLS_EINVAL; }
@@ -626,6 +627,9 @@ int stls_setup(int d, const int* nknots, const double* const* knots, const int* 
     return STLS_EINVAL;
   }
   int st = STLS_OK;
+  // mapped domain: spatial stencils, and for P^G the weighted FD factors
+  // (they replace dir[k].U and lam before the upload below)
+  if (geometry != STLS_GEOM_UNIT_BOX) st = mapped_host_setup(h, geometry, prec);
   for (int k = 0; k <= d && !st; ++k) {
     Dir& D = h->dir[k];
     DevDir& dd = h->dd[k];
@@ -670,12 +674,33 @@ int stls_setup(int d, const int* nknots, const double* const* knots, const int* 
     set_error("hipHostMalloc");
     st = STLS_ENOMEM;
   }
+  if (!st && geometry != STLS_GEOM_UNIT_BOX) st = mapped_upload(h);
   if (st) {
     free_ctx(h);
     return st;
   }
   *out = h;
   return STLS_OK;
+}
+
+int stls_setup(int d, const int* nknots, const double* const* knots, const int* degree, double kappa,
+               void* stream, stls_handle* out) {
+  return setup_common(d, nknots, knots, degree, kappa, stream, STLS_GEOM_UNIT_BOX, STLS_PREC_PARAMETRIC, out);
+}
+
+int stls_setup_mapped(int d, const int* nknots, const double* const* knots, const int* degree, double kappa,
+                      int geometry, int prec, void* stream, stls_handle* out) {
+  if (geometry != STLS_GEOM_QUARTER_ANNULUS && geometry != STLS_GEOM_ROTATED_QUARTER_ANNULUS) {
+    set_error("geometry must be STLS_GEOM_QUARTER_ANNULUS or STLS_GEOM_ROTATED_QUARTER_ANNULUS");
+    if (out) *out = nullptr;
+    return STLS_EINVAL;
+  }
+  if (prec != STLS_PREC_PARAMETRIC && prec != STLS_PREC_GEOMETRY) {
+    set_error("prec must be STLS_PREC_PARAMETRIC or STLS_PREC_GEOMETRY");
+    if (out) *out = nullptr;
+    return STLS_EINVAL;
+  }
+  return setup_common(d, nknots, knots, degree, kappa, stream, geometry, prec, out);
 }
 
 int stls_destroy(stls_handle h) {
@@ -722,7 +747,8 @@ int stls_get_factor(stls_handle h, int dir, int what, double* out, int64_t* coun
 int stls_set_kappa(stls_handle h, double kappa) {
   if (!h || !(kappa > 0.0) || !std::isfinite(kappa)) { set_error("bad handle or kappa"); return STLS_EINVAL; }
   h->kappa = kappa;
-  return upload_lambda_s(h);
+  const int st = upload_lambda_s(h);
+  return st ? st : mapped_update_sigma(h);  // P^G on a mapped domain: D depends on kappa
 }
 
 int stls_set_fd_precision(stls_handle h, int mode) {
@@ -733,6 +759,10 @@ int stls_set_fd_precision(stls_handle h, int mode) {
 
 int stls_set_fd_scaling(stls_handle h, int on) {
   if (!h) { set_error("NULL handle"); return STLS_EINVAL; }
+  if (h->geometry && on) {
+    set_error("mapped domains take their preconditioner (P or the scaled P^G) at stls_setup_mapped");
+    return STLS_EINVAL;
+  }
   h->fd_scale = on != 0;
   return STLS_OK;
 }
@@ -748,7 +778,7 @@ int stls_pcg_history(stls_handle h, double* out, int max, int* count) {
 
 static const char* kProfNames[PROF_COUNT] = {"fd_space", "fd_time", "mv_inner1",   "mv_inner2",   "mv_outer",
                                              "vec_xr",   "reduce",  "diff",        "fd_slab_fwd", "fd_slab_bwd",
-                                             "vec_p",    "misc"};
+                                             "vec_p",    "misc",    "mv_mapped"};
 
 int stls_set_profiling(stls_handle h, int on) {
   if (!h) { set_error("NULL handle"); return STLS_EINVAL; }

@@ -106,6 +106,7 @@ enum ProfId {
   PROF_FD_SLAB_BWD,   // FD slab pass, backward (writes s, partial sums of s . r)
   PROF_VEC_P,         // PCG direction update p = z + beta p
   PROF_MISC,          // other elementwise kernels (initial dot, diagonal scaling)
+  PROF_MV_MAPPED,     // matvec on a mapped domain (time band and spatial stencils)
   PROF_COUNT
 };
 
@@ -141,6 +142,16 @@ struct stls_ctx {
   bool bands_ready = false;        // rectangular bands on the device (uploaded at setup)
   bool diff_ready = false;         // and the full-space temporaries allocated
   double* noalloc_scratch = nullptr;  // this device's static workspace (stls_load_apply_noalloc)
+  // mapped spatial domain (stls_setup_mapped); geometry == STLS_GEOM_UNIT_BOX
+  // for the Kronecker path
+  int geometry = 0;
+  int geo_prec = 0;               // STLS_PREC_PARAMETRIC (P) or STLS_PREC_GEOMETRY (P^G)
+  int stencil = 0;                // entries per stencil row: prod_k (2 p_k + 1)
+  double* sten[3] = {nullptr, nullptr, nullptr};  // M_s, J_s, L_s as [stencil][ns] (device)
+  double* sigma = nullptr;        // (P^G) sigma_i = (Pbar_ii / A_ii)^(1/2), ndof (device)
+  std::vector<double> sdiag[3];   // diagonals of M_s, J_s, L_s (host, ns)
+  std::vector<double> hsten[3];   // host stencils between assembly and upload
+  std::vector<double> wdiag[stls::kMaxDim + 1][2];  // diagonals of the FD factors: space [M, J], time [K, M]
   stls::PcgScalars* scal = nullptr;
   stls::PcgScalars* scal_host = nullptr;  // pinned, 2 slots (convergence checks of alternate iterations)
   hipEvent_t check_ev[2] = {nullptr, nullptr};
@@ -190,6 +201,18 @@ int prec_apply_five_pass(stls_ctx* h, const double* r, double* s, const double* 
                          int* nparts, bool scale);
 int upload_diff_bands(stls_ctx* h);
 int ensure_diff_operands(stls_ctx* h);
+// Mapped domains (stls_geometry.cpp): host assembly of the pulled-back
+// spatial stencils, the geometry-weighted FD factors (replacing dir[k].U and
+// lam when the preconditioner is P^G) and the scaling vector; device side
+// in stls_mapped.hip.
+int mapped_host_setup(stls_ctx* h, int geometry, int prec);
+int mapped_upload(stls_ctx* h);
+int mapped_update_sigma(stls_ctx* h);
+int launch_mapped_matvec(stls_ctx* h, const double* x, double* y, const double* dot_with, double* partials,
+                         int* nparts);
+int launch_mapped_scale(stls_ctx* h, const double* x, double* y, const double* dot_with, double* partials,
+                        int* nparts);
+
 // Device address of the static workspace of the allocation-free entry points
 // on the current device (looked up once per device; stls_diff.hip).
 int resolve_noalloc_scratch(stls_ctx* h);

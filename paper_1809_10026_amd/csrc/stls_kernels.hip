@@ -725,6 +725,17 @@ static int prec_apply_plain(stls_ctx* h, const double* r, double* s, const doubl
 
 int launch_prec_apply(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
                       int* nparts) {
+  if (h->geometry && h->sigma) {
+    // P^G on a mapped domain: sigma o r, the chain with the weighted
+    // factors, sigma o s in place with the dot product
+    double* tmp = h->work[0];
+    int st = launch_mapped_scale(h, r, tmp, nullptr, nullptr, nullptr);
+    if (!st)
+      st = fd_five_pass_covers(h) ? prec_apply_five_pass(h, tmp, s, nullptr, nullptr, nullptr, false)
+                                  : prec_apply_plain(h, tmp, s, nullptr, nullptr, nullptr);
+    if (!st) st = launch_mapped_scale(h, s, s, dot_with, partials, nparts);
+    return st;
+  }
   if (fd_five_pass_covers(h))
     return prec_apply_five_pass(h, r, s, dot_with, partials, nparts, h->fd_scale);  // scaling fused
   if (!h->fd_scale) return prec_apply_plain(h, r, s, dot_with, partials, nparts);
@@ -1466,6 +1477,7 @@ static int launch_outer_dma(stls_ctx* h, const double* A, const double* B, const
 
 int launch_matvec(stls_ctx* h, const double* x, double* y, const double* dot_with, double* partials,
                   int* nparts) {
+  if (h->geometry) return launch_mapped_matvec(h, x, y, dot_with, partials, nparts);
   const int d = h->d;
   const int N = (int)h->ndof;
   double** w = h->work;

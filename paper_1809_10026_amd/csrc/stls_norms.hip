@@ -200,6 +200,7 @@ int stls_norm_points(stls_handle h, int dir, double* x, double* w, int* nq) {
 }
 
 int stls_error_norms(stls_handle h, const double* u, int nterms, const double* const* g, double* out) {
+  if (h && h->geometry) { set_error("stls_error_norms: unit box only (not available on a mapped domain)"); return STLS_EINVAL; }
   if (!h || !u || !g || !out || nterms < 1 || nterms > kMaxTerms) {
     set_error("bad handle, pointers or number of terms (1..64)");
     return STLS_EINVAL;
