@@ -348,7 +348,7 @@ __device__ inline unsigned short bf16_rne(float f) {
 }
 __device__ inline float bf16_to_float(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
 
-template <typename TI, typename TO, int NM, bool TRANS, bool FUSED, bool DOT>
+template <typename TI, typename TO, int NM, bool TRANS, bool FUSED, bool DOT, bool DIV>
 __global__ __launch_bounds__(kThreads) void fd_mode_bf16x3_kernel(
     const TI* __restrict__ X, TO* __restrict__ Y, int L, int n, int ncols, const unsigned short* __restrict__ Wh,
     const unsigned short* __restrict__ Wl, const unsigned short* __restrict__ W2h,
@@ -382,8 +382,9 @@ __global__ __launch_bounds__(kThreads) void fd_mode_bf16x3_kernel(
   };
   stage_w(Wh, Wl, 0);
   if constexpr (FUSED) stage_w(W2h, W2l, 1);
-  double lt[FUSED ? NM * 4 : 1];
-  if constexpr (FUSED) {
+  constexpr bool TIME = FUSED || DIV;  // the eigenvalue division of the time pass
+  double lt[TIME ? NM * 4 : 1];
+  if constexpr (TIME) {
 #pragma unroll
     for (int t = 0; t < NM; ++t)
 #pragma unroll
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(kThreads) void fd_mode_bf16x3_kernel(
       }
     }
     double ls = 1.0;
-    if constexpr (FUSED) ls = lam_s[min(c0 + ccol, ncols - 1)];
+    if constexpr (TIME) ls = lam_s[min(c0 + ccol, ncols - 1)];
     double dv[DOT ? NM * 4 : 1];
     if constexpr (DOT) {
 #pragma unroll
@@ -502,7 +503,9 @@ __global__ __launch_bounds__(kThreads) void fd_mode_bf16x3_kernel(
       for (int r = 0; r < 4; ++r) {
         int i, cc;
         out_pos(c0, t, r, i, cc);
-        const TO v = (TO)acc[t][r];
+        TO v;
+        if constexpr (DIV && !FUSED) v = (TO)((double)acc[t][r] / (lt[t * 4 + r] + ls));  // FP64, as the fused pass
+        else v = (TO)acc[t][r];
         if constexpr (DOT) dsum += (double)v * dv[t * 4 + r];
         if (cc < ncols && i < n) Y[(size_t)column_base(cc) + (size_t)i * L] = v;
       }
@@ -513,7 +516,16 @@ __global__ __launch_bounds__(kThreads) void fd_mode_bf16x3_kernel(
   }
 }
 
-template <typename TI, typename TO, bool TRANS, bool FUSED, bool DOT>
+// LDS bytes of the bf16 mode kernel: the operator (two for the fused time
+// pass) in bf16 hi + lo with padded rows, and the panel.
+static size_t bf16_shmem(const DevDir& D, bool fused) {
+  const int nm = D.npad / 16;
+  const int ldk = (nm + 1) / 2 * 32 + 8;
+  return sizeof(unsigned short) * ((fused ? 2 : 1) * 2 * (size_t)D.npad * ldk + 2 * (size_t)kCols * ldk) +
+         4 * sizeof(double) + 16;
+}
+
+template <typename TI, typename TO, bool TRANS, bool FUSED, bool DOT, bool DIV = false>
 static int launch_fd_bf16(stls_ctx* h, const TI* X, TO* Y, int L, int n, int ncols, int k, bool fwd, int k2,
                           const double* lam_t, const double* dotv, double* partials, int* nparts) {
   const DevDir& D = h->dd[k];
@@ -521,8 +533,7 @@ static int launch_fd_bf16(stls_ctx* h, const TI* X, TO* Y, int L, int n, int nco
   const int nk = (nm + 1) / 2, kpad = nk * 32, ldk = kpad + 8;
   if (kpad != D.kpad) { set_error("bf16 operand padding mismatch"); return STLS_EINVAL; }
   const int npanels = (ncols + kCols - 1) / kCols;
-  const size_t shmem = sizeof(unsigned short) * ((FUSED ? 2 : 1) * 2 * (size_t)D.npad * ldk + 2 * (size_t)kCols * ldk) +
-                       4 * sizeof(double) + 16;
+  const size_t shmem = bf16_shmem(D, FUSED);
   if (shmem > 160 * 1024) { set_error("direction too large for the bf16 FD kernel"); return STLS_EINVAL; }
   const int per_cu = std::max(1, std::min(4, (int)((160 * 1024) / shmem)));
   const int blocks = std::min(npanels, 256 * per_cu);
@@ -536,7 +547,7 @@ static int launch_fd_bf16(stls_ctx* h, const TI* X, TO* Y, int L, int n, int nco
                const unsigned short*, const double*, const double*, const double*, double*,
                const PcgScalars*) = nullptr;
 #define STLS_BF_PICK(NMV) \
-  case NMV: kern = fd_mode_bf16x3_kernel<TI, TO, NMV, TRANS, FUSED, DOT>; break;
+  case NMV: kern = fd_mode_bf16x3_kernel<TI, TO, NMV, TRANS, FUSED, DOT, DIV>; break;
   switch (nm) {
     STLS_BF_PICK(1) STLS_BF_PICK(2) STLS_BF_PICK(3) STLS_BF_PICK(4) STLS_BF_PICK(5) STLS_BF_PICK(6)
     STLS_BF_PICK(7) STLS_BF_PICK(8) STLS_BF_PICK(9) STLS_BF_PICK(10) STLS_BF_PICK(11) STLS_BF_PICK(12)
@@ -553,7 +564,7 @@ static int launch_fd_bf16(stls_ctx* h, const TI* X, TO* Y, int L, int n, int nco
                      h->lam_s, dotv, partials, h->gate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "fd_mode_bf16x3_kernel launch");
-  prof_end(h, FUSED ? PROF_FD_TIME : PROF_FD_SPACE);
+  prof_end(h, (FUSED || k == h->d) ? PROF_FD_TIME : PROF_FD_SPACE);
   return STLS_OK;
 }
 
@@ -578,10 +589,23 @@ static int prec_apply_bf16x3(stls_ctx* h, const double* r, double* s, const doub
     if (st) return st;
     L *= n;
   }
-  st = launch_fd_bf16<float, float, false, true, false>(h, buf[cur], buf[cur ^ 1], ns, nt, ns, d, true, d,
-                                                        h->dd[d].lam, nullptr, nullptr, nullptr);
-  if (st) return st;
-  cur ^= 1;
+  if (bf16_shmem(h->dd[d], true) <= 160 * 1024) {
+    st = launch_fd_bf16<float, float, false, true, false>(h, buf[cur], buf[cur ^ 1], ns, nt, ns, d, true, d,
+                                                          h->dd[d].lam, nullptr, nullptr, nullptr);
+    if (st) return st;
+    cur ^= 1;
+  } else {
+    // the two time operators do not fit in LDS together (n_t > 128): the
+    // forward product with the division, then the backward product
+    st = launch_fd_bf16<float, float, false, false, false, true>(h, buf[cur], buf[cur ^ 1], ns, nt, ns, d, true, 0,
+                                                                 h->dd[d].lam, nullptr, nullptr, nullptr);
+    if (st) return st;
+    cur ^= 1;
+    st = launch_fd_bf16<float, float, false, false, false>(h, buf[cur], buf[cur ^ 1], ns, nt, ns, d, false, 0,
+                                                           nullptr, nullptr, nullptr, nullptr);
+    if (st) return st;
+    cur ^= 1;
+  }
   for (int k = d - 1; k >= 0; --k) {
     const int n = h->dir[k].n;
     L /= n;

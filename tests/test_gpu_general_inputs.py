@@ -3,7 +3,8 @@ uniform, equal-degree benchmark shapes (§2.1 open knot vectors with uneven
 elements and repeated interior knots; §2.2 spaces with a space degree other
 than the time degree, as studied in §5.1 with p_s = p_t + 1; different
 degrees and sizes per space direction).  These route the matvec, the FD
-chain and the batched kernels through their general instances.
+chain and the batched kernels through their general instances, and a long
+time direction (n_t > 128) through the two-launch BF16x3 time pass.
 
 Knots: uneven elements from ``graded_open_knots`` with one interior knot of
 multiplicity p - 1 in space (C^1, the least regularity the least-squares
@@ -58,6 +59,10 @@ CASES = {
     "d3_ps4_pt3_uneven_n": ([(8, 4, False), (6, 4, False), (7, 4, False), (9, 3, False)], 1.0),
     # d = 3: the same with graded knots and repeated interior knots
     "d3_ps4_pt3_graded": ([(8, 4, True), (6, 4, True), (7, 4, True), (9, 3, True)], 0.4),
+    # d = 2: a long time direction (n_t = 141 > 128: the BF16x3 time pass
+    # splits into a forward product with the division and a backward product,
+    # since both time operators no longer fit in LDS together)
+    "d2_long_time": ([(6, 2, False), (5, 3, True), (139, 2, True)], 1.0),
 }
 
 

@@ -61,12 +61,15 @@ def test_table1_iteration_counts_large(nsub, p, its):
     assert it == its
 
 
-@pytest.mark.parametrize("nsub,p", [(64, 3), (64, 5)])
+@pytest.mark.parametrize("nsub,p", [(64, 3), (64, 5), (128, 2), (128, 3)])
 def test_mixed_precision_at_large_sizes(nsub, p):
-    """BF16x3 FD on the general kernels: the true residual (GPU matvec)
-    reaches the tolerance.  Low-precision products may cost iterations
-    (measured: 13 -> 18 at n_sub = 64, p = 3); the bound is the one of the
-    small-size mixed-precision test."""
+    """BF16x3 FD on the general kernels, up to Table 1's n_sub = 128 rows
+    (n_t = 129, 130: the time pass runs as two launches, the pair of time
+    operators being beyond the LDS budget): the true residual (GPU matvec)
+    reaches the tolerance.  Low-precision products cost iterations here, the
+    more the larger n (their relative error grows with the spread of the
+    eigenvalues; measured: 13 -> 18 at n_sub = 64, p = 3; 13 -> 17 at p = 5;
+    13 -> 20 at n_sub = 128, p = 2); the bound allows eight more than FP64."""
     assert stls is not None, "libstls.so is not built; run python paper_1809_10026_amd/build.py"
     knots, degs, b = _rhs(nsub, p)
     S = stls.Solver(knots, degs)
@@ -77,22 +80,4 @@ def test_mixed_precision_at_large_sizes(nsub, p):
     import torch
     true_rel = float(torch.linalg.norm(r) / torch.linalg.norm(b))
     print(f"n_sub {nsub} p {p}: fp64 {it64} its, bf16x3 {it} its, true relres {true_rel:.2e}", flush=True)
-    assert it <= it64 + 6 and true_rel < 2e-8
-
-
-def test_bf16_time_pass_beyond_its_lds_budget_fails_loudly():
-    """n_sub = 128, p = 2: the time direction (n_t = 129) is beyond the LDS
-    budget of the general BF16x3 time kernel; the solve reports STLS_EINVAL
-    with a message instead of launching, and the handle keeps working in
-    FP64."""
-    assert stls is not None, "libstls.so is not built; run python paper_1809_10026_amd/build.py"
-    import torch
-    knots, degs = problem_knots(3, 128, 2)
-    S = stls.Solver(knots, degs)
-    b = torch.ones(S.ndof, dtype=torch.float64, device="cuda")
-    S.set_fd_precision(stls.STLS_FD_BF16X3)
-    with pytest.raises(stls.StlsError, match="too large"):
-        S.solve(b, rtol=1e-8, maxit=5)
-    S.set_fd_precision(stls.STLS_FD_FP64)
-    _, it, rel = S.solve(b, rtol=1e-2, maxit=50, raise_on_noconv=False)
-    assert it >= 1 and rel <= 1e-2
+    assert it <= it64 + 8 and true_rel < 2e-8
