@@ -73,7 +73,20 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)
+    build_mem_patterns()
     return LIB
+
+
+def build_mem_patterns() -> str:
+    """The memory-pattern reference executable (access orders of the hot
+    kernels without their arithmetic; see mem_patterns.hip)."""
+    exe = os.path.join(HERE, "mem_patterns")
+    cmd = [hipcc(), *HIP_FLAGS, "-x", "hip", os.path.join(HERE, "mem_patterns.hip"), "-o", exe + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("building mem_patterns failed:\n" + r.stderr)
+    os.replace(exe + ".tmp", exe)
+    return exe
 
 
 if __name__ == "__main__":
