@@ -53,8 +53,12 @@ typedef enum stls_status {
 typedef enum stls_fd_precision {
   STLS_FD_FP64 = 0,    /* n-mode products in FP64 (MFMA f64) */
   STLS_FD_FP32 = 1,    /* n-mode products and intermediates in FP32 (MFMA f32) */
-  STLS_FD_BF16X3 = 2   /* FP32 operands split into bf16 hi+lo, three bf16 MFMA
+  STLS_FD_BF16X3 = 2,  /* FP32 operands split into bf16 hi+lo, three bf16 MFMA
                           products (hi*hi + hi*lo + lo*hi), FP32 accumulation */
+  STLS_FD_ASYM = 3     /* asymmetric: forward space products (Algorithm 1 step 2)
+                          in FP32; the time products, the eigenvalue division
+                          (step 3) and the backward space products (step 4) in
+                          FP64 */
 } stls_fd_precision;
 
 /*
@@ -142,7 +146,9 @@ int stls_get_factor(stls_handle h, int dir, int what, double* out, int64_t* coun
 int stls_set_kappa(stls_handle h, double kappa);
 
 /* Select the arithmetic of the FD n-mode products (stls_fd_precision).
- * The eigenvalue division, PCG vectors and dot products stay FP64. */
+ * The eigenvalue division, PCG vectors and dot products stay FP64.  The
+ * asymmetric mode runs the general (one product per pass) kernels on every
+ * shape.  Returns STLS_EINVAL for an unknown mode. */
 int stls_set_fd_precision(stls_handle h, int mode);
 
 /*

@@ -18,7 +18,7 @@ import os
 import numpy as np
 
 __all__ = [
-    "LIB_PATH", "STLS_OK", "STLS_FD_FP64", "STLS_FD_FP32", "STLS_FD_BF16X3", "StlsError",
+    "LIB_PATH", "STLS_OK", "STLS_FD_FP64", "STLS_FD_FP32", "STLS_FD_BF16X3", "STLS_FD_ASYM", "StlsError",
     "stls_setup", "stls_destroy", "stls_get_shape", "stls_get_factor", "stls_set_kappa",
     "stls_set_fd_precision", "stls_set_fd_scaling", "stls_prec_apply", "stls_matvec", "stls_pcg_solve",
     "stls_pcg_history", "stls_norm_points", "stls_error_norms", "stls_set_profiling", "stls_profile", "stls_profile_reset",
@@ -39,7 +39,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 STLS_OK, STLS_EINVAL, STLS_ENOMEM, STLS_EHIP, STLS_ENOCONV, STLS_ENAN, STLS_EBREAKDOWN = 0, -1, -2, -3, -4, -5, -6
-STLS_FD_FP64, STLS_FD_FP32, STLS_FD_BF16X3 = 0, 1, 2
+STLS_FD_FP64, STLS_FD_FP32, STLS_FD_BF16X3, STLS_FD_ASYM = 0, 1, 2, 3
 STLS_GEOM_UNIT_BOX, STLS_GEOM_QUARTER_ANNULUS, STLS_GEOM_ROTATED_QUARTER_ANNULUS = 0, 1, 2
 STLS_PREC_PARAMETRIC, STLS_PREC_GEOMETRY = 0, 1
 # batch tuning fields, in the order of enum stls_batch_tune_field

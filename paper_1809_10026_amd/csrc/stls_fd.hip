@@ -716,7 +716,7 @@ int five_pass_scaled(stls_ctx* h, const double* r, double* s, const double* dot_
 // addressable by one buffer resource (byte offsets below 2^31; out-of-range
 // lanes use 0x7fffffff).
 bool fd_five_pass_covers(const stls_ctx* h) {
-  if (h->d != 3) return false;
+  if (h->d != 3 || h->fd_mode == STLS_FD_ASYM) return false;
   for (int k = 0; k <= 3; ++k)
     if (h->dir[k].n > 64) return false;
   if (h->dir[0].n % 2 != 0 || h->dd[0].npad != h->dd[1].npad) return false;

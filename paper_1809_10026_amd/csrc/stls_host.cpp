@@ -752,7 +752,7 @@ int stls_set_kappa(stls_handle h, double kappa) {
 }
 
 int stls_set_fd_precision(stls_handle h, int mode) {
-  if (!h || mode < STLS_FD_FP64 || mode > STLS_FD_BF16X3) { set_error("bad handle or precision mode"); return STLS_EINVAL; }
+  if (!h || mode < STLS_FD_FP64 || mode > STLS_FD_ASYM) { set_error("bad handle or precision mode"); return STLS_EINVAL; }
   h->fd_mode = mode;
   return STLS_OK;
 }

@@ -683,6 +683,63 @@ static int prec_apply_t(stls_ctx* h, const double* r, double* s, const double* d
   return STLS_OK;
 }
 
+// Asymmetric chain: the forward space products in FP32 (MFMA f32, FP32
+// intermediates); the fused time pass (both time products and the
+// eigenvalue division) and the backward space products in FP64.  Rounding in
+// the backward half is what costs PCG iterations; the forward half tolerates
+// FP32 with little effect on the count.
+static int prec_apply_asym(stls_ctx* h, const double* r, double* s, const double* dot_with, double* partials,
+                           int* nparts) {
+  const int d = h->d;
+  const int nt = h->dir[d].n;
+  const int ns = (int)h->ns;
+  float* fb[2] = {reinterpret_cast<float*>(h->fdbuf[0]), reinterpret_cast<float*>(h->fdbuf[1])};
+  double* db[2] = {h->fdbuf[0], h->fdbuf[1]};
+  int st, cur = 0, L = 1;
+  for (int k = 0; k < d; ++k) {
+    const int n = h->dir[k].n;
+    const int ncols = (int)(h->ndof / n);
+    if (k == 0)
+      st = launch_fd_mode<float, double, float, true, false, false>(h, r, fb[cur], L, n, ncols, h->dd[k].Afwd32,
+                                                                    nullptr, h->dd[k].npad, nullptr, nullptr, nullptr,
+                                                                    nullptr);
+    else {
+      st = launch_fd_mode<float, float, float, false, false, false>(h, fb[cur], fb[cur ^ 1], L, n, ncols,
+                                                                    h->dd[k].Afwd32, nullptr, h->dd[k].npad, nullptr,
+                                                                    nullptr, nullptr, nullptr);
+      cur ^= 1;
+    }
+    if (st) return st;
+    L *= n;
+  }
+  st = launch_fd_mode<double, float, double, false, true, false>(h, fb[cur], db[cur ^ 1], ns, nt, ns, h->dd[d].Afwd64,
+                                                                 h->dd[d].Abwd64, h->dd[d].npad, h->dd[d].lam, nullptr,
+                                                                 nullptr, nullptr);
+  if (st) return st;
+  cur ^= 1;
+  for (int k = d - 1; k >= 0; --k) {
+    const int n = h->dir[k].n;
+    L /= n;
+    const int ncols = (int)(h->ndof / n);
+    if (k == 0)
+      st = dot_with ? launch_fd_mode<double, double, double, true, false, true>(h, db[cur], s, L, n, ncols,
+                                                                                h->dd[k].Abwd64, nullptr, h->dd[k].npad,
+                                                                                nullptr, dot_with, partials, nparts)
+                    : launch_fd_mode<double, double, double, true, false, false>(h, db[cur], s, L, n, ncols,
+                                                                                 h->dd[k].Abwd64, nullptr,
+                                                                                 h->dd[k].npad, nullptr, nullptr,
+                                                                                 nullptr, nparts);
+    else {
+      st = launch_fd_mode<double, double, double, false, false, false>(h, db[cur], db[cur ^ 1], L, n, ncols,
+                                                                       h->dd[k].Abwd64, nullptr, h->dd[k].npad,
+                                                                       nullptr, nullptr, nullptr, nullptr);
+      cur ^= 1;
+    }
+    if (st) return st;
+  }
+  return STLS_OK;
+}
+
 // Diagonal scaling around the FD chains (§4.4, closing definition):
 // y_i = sigma_i x_i with sigma_i = (P_ii / A_ii)^1/2 in FP64, the multi-index
 // decoded from the colex position; optional partial sums of y . dotv (one
@@ -743,6 +800,7 @@ static int prec_apply_plain(stls_ctx* h, const double* r, double* s, const doubl
     case STLS_FD_FP64: return prec_apply_t<double>(h, r, s, dot_with, partials, nparts);
     case STLS_FD_FP32: return prec_apply_t<float>(h, r, s, dot_with, partials, nparts);
     case STLS_FD_BF16X3: return prec_apply_bf16x3(h, r, s, dot_with, partials, nparts);
+    case STLS_FD_ASYM: return prec_apply_asym(h, r, s, dot_with, partials, nparts);
     default: set_error("FD precision mode not available"); return STLS_EINVAL;
   }
 }

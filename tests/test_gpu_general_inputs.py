@@ -11,7 +11,8 @@ multiplicity p - 1 in space (C^1, the least regularity the least-squares
 method admits) and p in time (C^0).  Tolerances are those of the uniform
 parity tests: matvec 1e-13; FD in FP64 by its backward error (1e-14) and a
 forward difference within max(1e-12, 10 eps cond(P)); FP32 products 2e-5;
-BF16x3 products 5e-4 (cond(U) stays below ~20 here); PCG iteration counts
+BF16x3 products 5e-4 (cond(U) stays below ~20 here); the asymmetric mode
+(FP32 forward products) 2e-5; PCG iteration counts
 within one of the oracle's and solutions within the tolerance times the
 condition bound 2d of the preconditioned system (§4.2.1).
 """
@@ -136,7 +137,7 @@ def test_prec_apply_general(name, scaled):
     cond = normP * _power(lambda v: osys.vec(G.apply(v) if scaled else fdo.apply(v)), P.ndof)
     assert np.linalg.norm(Pv(s) - r) / (normP * np.linalg.norm(s)) < 1e-14
     assert rel_err(s, ref) < max(1e-12, 10 * np.finfo(float).eps * cond)
-    for mode, tol in ((stls.STLS_FD_FP32, 2e-5), (stls.STLS_FD_BF16X3, 5e-4)):
+    for mode, tol in ((stls.STLS_FD_FP32, 2e-5), (stls.STLS_FD_BF16X3, 5e-4), (stls.STLS_FD_ASYM, 2e-5)):
         S.set_fd_precision(mode)
         err = rel_err(to_host(S.prec_apply(to_dev(r))), ref)
         assert err < tol, (mode, err)
@@ -154,7 +155,7 @@ def test_pcg_general(name):
     xo = to_host(x)
     assert abs(it - info["iters"]) <= 1 and rel <= 1e-10
     assert rel_err(xo, x_ref) < 2 * d * 10 * 1e-10
-    for mode in (stls.STLS_FD_FP32, stls.STLS_FD_BF16X3):
+    for mode in (stls.STLS_FD_FP32, stls.STLS_FD_BF16X3, stls.STLS_FD_ASYM):
         S.set_fd_precision(mode)
         x, it_m, rel = S.solve(to_dev(b), rtol=1e-8, maxit=300)
         xo = to_host(x)

@@ -152,7 +152,21 @@ def test_prec_apply_bf16x3_error_bound(d, nel, p, kappa):
     assert rel_err(s, s_ref) < 5e-4
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("d,nel,p,kappa", CASES)
+def test_prec_apply_asymmetric_error_bound(d, nel, p, kappa):
+    """Asymmetric FD: the d forward space products in FP32, the time pass
+    and the backward products in FP64; the error is that of the FP32 forward
+    half (the FP32 bound above)."""
+    S = _lib().Solver(*problem_knots(d, nel, p), kappa=kappa)
+    P = osys.Problem(*problem_knots(d, nel, p), kappa=kappa)
+    S.set_fd_precision(stls.STLS_FD_ASYM)
+    r = uniform_pm1(P.ndof, 15)
+    s = to_host(S.prec_apply(to_dev(r)))
+    s_ref = osys.vec(ofd.FD(P).apply(r))
+    assert rel_err(s, s_ref) < 2e-5
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
 @pytest.mark.parametrize("d,nel,p", [(2, 16, 3), (3, 8, 4)])
 def test_pcg_mixed_precision_reaches_fp64_tolerance(mode, d, nel, p):
     """Low-precision FD inside the FP64 PCG still reaches rtol = 1e-8 on the

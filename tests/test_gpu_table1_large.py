@@ -81,3 +81,25 @@ def test_mixed_precision_at_large_sizes(nsub, p):
     true_rel = float(torch.linalg.norm(r) / torch.linalg.norm(b))
     print(f"n_sub {nsub} p {p}: fp64 {it64} its, bf16x3 {it} its, true relres {true_rel:.2e}", flush=True)
     assert it <= it64 + 8 and true_rel < 2e-8
+
+
+@pytest.mark.parametrize("nsub,p", [(64, 3), (128, 3)])
+def test_asymmetric_precision_at_large_sizes(nsub, p):
+    """The asymmetric FD (FP32 forward space products, FP64 time pass and
+    backward products) at the Table 1 sizes where BF16x3 and FP32 cost
+    iterations: the true residual reaches the tolerance in at most two
+    iterations more than FP64."""
+    assert stls is not None, "libstls.so is not built; run python paper_1809_10026_amd/build.py"
+    knots, degs, b = _rhs(nsub, p)
+    S = stls.Solver(knots, degs)
+    _, it64, _ = S.solve(b, rtol=1e-8, maxit=100)
+    S.set_fd_precision(stls.STLS_FD_FP32)
+    _, it32, _ = S.solve(b, rtol=1e-8, maxit=100)
+    S.set_fd_precision(stls.STLS_FD_ASYM)
+    x, it, rel = S.solve(b, rtol=1e-8, maxit=100)
+    r = b - S.matvec(x)
+    import torch
+    true_rel = float(torch.linalg.norm(r) / torch.linalg.norm(b))
+    print(f"n_sub {nsub} p {p}: fp64 {it64} its, fp32 {it32} its, asymmetric {it} its, true relres {true_rel:.2e}",
+          flush=True)
+    assert it <= it64 + 2 and true_rel < 2e-8
