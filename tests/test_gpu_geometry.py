@@ -129,6 +129,28 @@ def test_table2_pg_against_p_on_the_gpu():
         assert its[0] >= 3 * its[1]
 
 
+@pytest.mark.parametrize("nsub", [16, 32])
+def test_table2_sizes_pg_against_p(nsub):
+    """Rotated quarter annulus at Table 2's n_sub = 16 and 32, p = 2, on the
+    GPU alone (the oracle's mapped solve is out of reach at 1.1 M unknowns):
+    both preconditioners reach the tolerance on the true residual, and P^G
+    needs at least three times fewer iterations than P (paper: 126 vs 35 and
+    142 vs 42; our parametrisation is not the paper's NURBS, so the counts
+    agree in ratio, not exactly)."""
+    import torch
+    its = []
+    for prec in (stls.STLS_PREC_PARAMETRIC, stls.STLS_PREC_GEOMETRY):
+        knots, degs = problem_knots(3, nsub, 2)
+        S = stls.Solver(knots, degs, geometry=stls.STLS_GEOM_ROTATED_QUARTER_ANNULUS, prec=prec)
+        b = to_dev(uniform_pm1(S.ndof, 1))
+        x, it, rel = S.solve(b, rtol=1e-8, maxit=3000)
+        true_rel = float(torch.linalg.norm(b - S.matvec(x)) / torch.linalg.norm(b))
+        assert rel <= 1e-8 and true_rel < 2e-8, (prec, rel, true_rel)
+        its.append(it)
+    print(f"rotated quarter annulus n_sub {nsub} p 2: P {its[0]}, P^G {its[1]}", flush=True)
+    assert its[0] >= 3 * its[1]
+
+
 def _q(x):
     X, Y = x[:, 0], x[:, 1]
     s = X * X + Y * Y
