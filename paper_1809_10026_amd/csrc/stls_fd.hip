@@ -399,7 +399,9 @@ __global__ __launch_bounds__(256) void fd_slab_kernel(
 // One wave handles 16 consecutive columns at a time, its B fragments loaded
 // straight from global memory (8 consecutive k of one column per lane), two
 // such units prefetched into registers (two register sets, unrolled, so that
-// no copy of an in-flight value forces an early wait).  FUSED: time mode,
+// no copy of an in-flight value forces an early wait); the FP64 mode-3 pass
+// prefetches one unit, which fits it in 128 registers and two workgroups per
+// CU (37.9 -> 30.6 us at d = 3, p = 4, 48 elements).  FUSED: time mode,
 //   Q(i, c) = (W X)(i, c) / (lambda_t[i] + lambda_s[c])  (FP64 division,
 //             quotient rounded to T),
 //   Y = W2 Q,
@@ -409,9 +411,10 @@ __global__ __launch_bounds__(256) void fd_slab_kernel(
 constexpr int kStridedWaves = 8;
 constexpr int kStridedDepth = 2;
 
+// waves per SIMD the registers must allow (the second launch-bounds argument)
 template <int PR, bool FUSED, bool WL>
 constexpr int strided_min_blocks() {
-  return PR == kPrecF64 ? 1 : ((WL && !FUSED) ? 4 : 2);
+  return PR == kPrecF64 ? (FUSED ? 1 : 4) : ((WL && !FUSED) ? 4 : 2);
 }
 
 template <int PR, int NM, bool FUSED, bool WL>
@@ -429,7 +432,7 @@ __global__ __launch_bounds__(kStridedWaves * 64, (strided_min_blocks<PR, FUSED, 
   constexpr int NK = (NM + 1) / 2;
   constexpr int KPAD = NK * 32;
   constexpr int LDS_S = KPAD + 4;
-  constexpr int DEPTH = kStridedDepth;
+  constexpr int DEPTH = (PR == kPrecF64 && !FUSED) ? 1 : kStridedDepth;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, cl = lane & 15;
