@@ -292,6 +292,8 @@ def main():
             log(f"{m}: error vs oracle solution {err_vs_oracle[m]['rel_l2']:.2e} (relative 2-norm)")
         err_norms["oracle_cpu"] = cpu_error_norms()
         lifting["oracle_cpu"] = cpu_lifting(knots, degs)
+        geometry["oracle_cpu"] = cpu_mapped_geometry(geometry)
+    geometry.get("small", {}).pop("solution", None)
 
     t_mixed, t_fp64 = res[mixed]["time_s"], res["fp64"]["time_s"]
     out = {
@@ -417,21 +419,27 @@ def gpu_batch(stls, torch, steps=3):
                          "default_seconds": dt_default}}
 
 
-def gpu_geometry(stls, torch, n_sub=16, p=2, reps=3):
+def gpu_geometry(stls, torch, n_sub=32, p=2, reps=3, mv_reps=50, small=12):
     """Mapped domain (§4.4, §5.2 Table 2): the rotated quarter annulus,
-    n_sub = 16, p_s = p_t = 2 (ndof 16^3 x 17 = 69,632), right-hand side
+    n_sub = 32, p_s = p_t = 2 (ndof 32^3 x 33 = 1,081,344), right-hand side
     U[-1, 1] (seed 1), PCG to 1e-8 with the parametric P and with the
-    geometry-aware P^G (FP64 FD; P^G also with bf16x3 FD).  Host setup
-    (stencil assembly, Algorithm 2, eigendecompositions) timed apart."""
+    geometry-aware P^G (FP64 FD; P^G also with bf16x3 FD).  Setup (stencil
+    assembly on the device, Algorithm 2 and the eigendecompositions on the
+    host) timed apart.  The mapped matvec is priced with its algorithmic
+    bytes: the three stencils read once (3 S n_s doubles, S = (2p+1)^3) plus
+    x read and y written.  The same P^G solve at n_sub = 12 is timed beside
+    the oracle's (cpu_mapped_geometry)."""
     from stls_inputs import problem_knots, uniform_pm1
     knots, degs = problem_knots(3, n_sub, p)
     out = {"workload": f"rotated quarter annulus, n_sub={n_sub}, p={p}, RHS U[-1,1] seed 1, rtol 1e-8",
-           "table2_paper_iterations": {"P": 126, "P^G": 35}}
+           "table2_paper_iterations": {"P": 142, "P^G": 42}}
     for name, prec, mode in (("P", stls.STLS_PREC_PARAMETRIC, stls.STLS_FD_FP64),
                              ("P^G", stls.STLS_PREC_GEOMETRY, stls.STLS_FD_FP64),
                              ("P^G bf16x3", stls.STLS_PREC_GEOMETRY, stls.STLS_FD_BF16X3)):
+        torch.cuda.synchronize()
         t = time.perf_counter()
         S = stls.Solver(knots, degs, geometry=stls.STLS_GEOM_ROTATED_QUARTER_ANNULUS, prec=prec)
+        torch.cuda.synchronize()
         setup_s = time.perf_counter() - t
         S.set_fd_precision(mode)
         b = torch.as_tensor(uniform_pm1(S.ndof, 1)).cuda()
@@ -446,8 +454,74 @@ def gpu_geometry(stls, torch, n_sub=16, p=2, reps=3):
         out[name] = {"ndof": S.ndof, "iters": it, "relres": rel, "seconds": dt, "setup_s": setup_s,
                      "dof_per_s": S.ndof / dt}
         log(f"mapped domain {name}: {it} iterations, {dt*1e3:.2f} ms, setup {setup_s:.2f} s")
+        if name == "P^G":
+            y = torch.empty_like(b)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            for fn, key in ((lambda: S.matvec(b, out=y), "matvec_us"), (lambda: S.prec_apply(b, out=y), "prec_apply_us")):
+                fn()
+                torch.cuda.synchronize()
+                ev[0].record()
+                for _ in range(mv_reps):
+                    fn()
+                ev[1].record()
+                torch.cuda.synchronize()
+                out[name][key] = ev[0].elapsed_time(ev[1]) / mv_reps * 1e3
+            n_s = S.ndof // (n_sub + p - 1)
+            sten = (2 * p + 1) ** 3
+            nbytes = 8 * (3 * sten * n_s + 2 * S.ndof)
+            achieved = nbytes / (out[name]["matvec_us"] * 1e-6) / 1e9
+            out["matvec_roofline"] = {"kernel": "mapped matvec: mapped_space_kernel + mapped_time_kernel",
+                                      "bound": "hbm", "algorithmic_bytes": nbytes, "achieved": round(achieved, 1),
+                                      "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+                                      "frac": round(achieved / PEAK["hbm_GBs"], 4),
+                                      "note": "three stencils of (2p+1)^3 entries per spatial row read once, "
+                                              "x read and y written; the kernels move U and V (16 B/DOF each way) "
+                                              "and re-read stencil rows once per chunk of time slices"}
+            log(f"mapped matvec {out[name]['matvec_us']:.1f} us, P^G apply {out[name]['prec_apply_us']:.1f} us, "
+                f"{achieved:.0f} GB/s algorithmic")
         S.close()
+    # the same P^G solve at n_sub = small, timed beside the oracle's
+    knots_s, degs_s = problem_knots(3, small, p)
+    S = stls.Solver(knots_s, degs_s, geometry=stls.STLS_GEOM_ROTATED_QUARTER_ANNULUS, prec=stls.STLS_PREC_GEOMETRY)
+    b = torch.as_tensor(uniform_pm1(S.ndof, 1)).cuda()
+    x = torch.empty_like(b)
+    S.solve(b, 1e-8, 3000, out=x)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        _, it, rel = S.solve(b, 1e-8, 3000, out=x)
+    torch.cuda.synchronize()
+    out["small"] = {"n_sub": small, "ndof": S.ndof, "iters": it, "seconds": (time.perf_counter() - t) / reps,
+                    "solution": x.cpu().numpy()}
+    S.close()
     return out
+
+
+def cpu_mapped_geometry(geometry, p=2):
+    """The oracle's P^G-PCG on the rotated quarter annulus at the small n_sub
+    of the GPU leg (numpy, host cores): assembly timed apart, the solve to
+    1e-8, and the error of the GPU's solution against it."""
+    import numpy as np
+
+    from oracle import geometry as geo, pcg as opcg
+    from stls_inputs import problem_knots, uniform_pm1
+    small = geometry["small"]
+    knots, degs = problem_knots(3, small["n_sub"], p)
+    t = time.perf_counter()
+    MP = geo.MappedProblem(geo.RotatedQuarterAnnulus(), knots, degs)
+    pre = geo.GeometryPreconditioner(MP)
+    setup = time.perf_counter() - t
+    b = uniform_pm1(MP.ndof, 1)
+    t = time.perf_counter()
+    xo, info = opcg.pcg(MP.matvec, pre.apply, b, 1e-8, maxit=3000)
+    dt = time.perf_counter() - t
+    xg = small.pop("solution")
+    err = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
+    log(f"cpu mapped P^G solve (n_sub {small['n_sub']}): {info['iters']} iterations, {dt:.2f} s "
+        f"(setup {setup:.1f} s); GPU solution error {err:.2e}")
+    return {"kind": "oracle", "workload": f"rotated quarter annulus, n_sub={small['n_sub']}, p={p}, P^G, rtol 1e-8",
+            "ndof": MP.ndof, "iters": info["iters"], "seconds": dt, "setup_s": setup,
+            "gpu_seconds": small["seconds"], "gpu_iters": small["iters"], "gpu_vs_oracle_rel_l2": err}
 
 
 def gpu_lifting(stls, torch, knots, degs, reps=20):

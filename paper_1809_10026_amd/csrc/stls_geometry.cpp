@@ -6,16 +6,14 @@
 // Kronecker structure of §4.1,
 //   A = K_t (x) M_s + kappa^2 M_t (x) J_s + kappa W_t (x) L_s,
 // with sparse spatial factors M_s = int B_i B_j, L_s = int grad B_i . grad B_j
-// and J_s = int Lap B_i Lap B_j over Omega.  They are assembled here by
-// tensor Gauss quadrature in the parametric domain (p + 3 points per
-// non-empty span: the integrands carry the geometry and are not
-// polynomial) and stored as stencils: row i of the restricted tensor basis
-// holds its prod_k (2 p_k + 1) entries at the column offsets o in
-// [-p_k, p_k]^d, colexicographic in o (zero where the column leaves the
-// box).  Physical derivatives of v = v^ o G^{-1}:
-//   grad v . grad w = sum_ab g^ab d_a v^ d_b w^,   g^ab = grad eta_a . grad eta_b,
-//   Lap v = sum_ab g^ab d_a d_b v^ + sum_j (Lap eta_j) d_j v^,
-//   Lap eta_j = -sum_ab g^ab [J^{-1} d_a d_b G]_j.
+// and J_s = int Lap B_i Lap B_j over Omega.  They are assembled on the
+// device (stls_mapped.hip, metric terms in stls_geomap.h) by tensor Gauss
+// quadrature in the parametric domain (p + 3 points per non-empty span: the
+// integrands carry the geometry and are not polynomial) and stored as
+// stencils: row i of the restricted tensor basis holds its
+// prod_k (2 p_k + 1) entries at the column offsets o in [-p_k, p_k]^d,
+// colexicographic in o (zero where the column leaves the box).  This file
+// prepares the quadrature data of the space directions.
 //
 // Preconditioner on the mapped domain (§4.4): either the parametric P of
 // §4.2 (the unit-box factors; G ignored) or P^G = D^1/2 Pbar^G D^1/2 with
@@ -31,115 +29,14 @@
 #include <algorithm>
 #include <cmath>
 #include <string>
-#include <thread>
 #include <vector>
 
+#include "stls_geomap.h"
 #include "stls_internal.h"
 
 namespace stls {
 
 namespace {
-
-constexpr double kHalfPi = 1.57079632679489661923;
-
-// Jacobian J[i][a] = d x_i / d eta_a and Hessian H[i][a][b] of the map.
-void quarter_annulus(const double* e, double J[3][3], double H[3][3][3]) {
-  const double A = kHalfPi, r = 1.0 + e[0], th = A * e[1];
-  const double c = std::cos(th), s = std::sin(th);
-  J[0][0] = c;
-  J[0][1] = -A * r * s;
-  J[1][0] = s;
-  J[1][1] = A * r * c;
-  for (int i = 0; i < 2; ++i)
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) H[i][a][b] = 0.0;
-  H[0][0][1] = H[0][1][0] = -A * s;
-  H[0][1][1] = -A * A * r * c;
-  H[1][0][1] = H[1][1][0] = A * c;
-  H[1][1][1] = -A * A * r * s;
-}
-
-// quarter annulus (x0, y0)(eta_1, eta_2) revolved by pi/2 about y = -1, z = 0:
-// x = x0, y = -1 + rho cos(phi), z = rho sin(phi), rho = y0 + 1, phi = (pi/2) eta_3
-void rotated_quarter_annulus(const double* e, double J[3][3], double H[3][3][3]) {
-  double J0[3][3], H0[3][3][3];
-  quarter_annulus(e, J0, H0);
-  const double A = kHalfPi, r = 1.0 + e[0], y0 = r * std::sin(A * e[1]);
-  const double rho = y0 + 1.0, ph = A * e[2], c = std::cos(ph), s = std::sin(ph);
-  for (int i = 0; i < 3; ++i)
-    for (int a = 0; a < 3; ++a) {
-      J[i][a] = 0.0;
-      for (int b = 0; b < 3; ++b) H[i][a][b] = 0.0;
-    }
-  for (int a = 0; a < 2; ++a) {
-    J[0][a] = J0[0][a];
-    J[1][a] = J0[1][a] * c;
-    J[2][a] = J0[1][a] * s;
-    for (int b = 0; b < 2; ++b) {
-      H[0][a][b] = H0[0][a][b];
-      H[1][a][b] = H0[1][a][b] * c;
-      H[2][a][b] = H0[1][a][b] * s;
-    }
-    H[1][a][2] = H[1][2][a] = -A * J0[1][a] * s;
-    H[2][a][2] = H[2][2][a] = A * J0[1][a] * c;
-  }
-  J[1][2] = -A * rho * s;
-  J[2][2] = A * rho * c;
-  H[1][2][2] = -A * A * rho * c;
-  H[2][2][2] = -A * A * rho * s;
-}
-
-struct Metric {
-  double det;        // |det J|
-  double g[3][3];    // g^ab
-  double lap[3];     // Lap eta_j
-};
-
-void metric_at(int geom, int d, const double* e, Metric& m) {
-  double J[3][3], H[3][3][3];
-  if (geom == 1) quarter_annulus(e, J, H);
-  else rotated_quarter_annulus(e, J, H);
-  double Ji[3][3];  // Ji[a][i] = d eta_a / d x_i
-  if (d == 2) {
-    const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-    m.det = std::fabs(det);
-    Ji[0][0] = J[1][1] / det;
-    Ji[0][1] = -J[0][1] / det;
-    Ji[1][0] = -J[1][0] / det;
-    Ji[1][1] = J[0][0] / det;
-  } else {
-    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-    m.det = std::fabs(det);
-    Ji[0][0] = c00 / det;
-    Ji[1][0] = c01 / det;
-    Ji[2][0] = c02 / det;
-    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
-    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
-    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
-    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
-    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
-    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
-  }
-  for (int a = 0; a < d; ++a)
-    for (int b = 0; b < d; ++b) {
-      double v = 0.0;
-      for (int i = 0; i < d; ++i) v += Ji[a][i] * Ji[b][i];
-      m.g[a][b] = v;
-    }
-  for (int j = 0; j < d; ++j) {
-    double v = 0.0;
-    for (int a = 0; a < d; ++a)
-      for (int b = 0; b < d; ++b) {
-        double t = 0.0;
-        for (int i = 0; i < d; ++i) t += Ji[j][i] * H[i][a][b];
-        v += m.g[a][b] * t;
-      }
-    m.lap[j] = -v;
-  }
-}
 
 // Quadrature points of one direction: per non-empty span, q Gauss points
 // with the values and first two derivatives of the span's p + 1 functions.
@@ -148,7 +45,6 @@ struct Quad1 {
   std::vector<int> span;         // knot span index of each non-empty span
   std::vector<double> x, w;      // points and weights (span-major)
   std::vector<double> v;         // [point][3][p+1]
-  std::vector<int> first_span;   // for each full function f: first non-empty span index (in span[]) with f in support
 };
 
 void build_quad(const Dir& D, int q, Quad1& Q) {
@@ -289,173 +185,24 @@ int mapped_host_setup(stls_ctx* h, int geometry, int prec) {
   }
   h->geometry = geometry;
   h->geo_prec = prec;
-  // --- quadrature of the spatial factors
+  // --- quadrature of the spatial factors; the stencils are assembled on the device
   Quad1 Q[kMaxDim];
-  size_t npts = 1;
-  int ncol[kMaxDim], bwk[kMaxDim], n[kMaxDim];
+  MappedQuad mq;
+  mq.d = d;
+  mq.geom = geometry;
   for (int k = 0; k < d; ++k) {
     build_quad(h->dir[k], h->dir[k].p + 3, Q[k]);
-    ncol[k] = (int)Q[k].x.size();
-    npts *= (size_t)ncol[k];
-    bwk[k] = 2 * h->dir[k].p + 1;
-    n[k] = h->dir[k].n;
+    mq.nel[k] = (int)Q[k].span.size();
+    mq.q[k] = Q[k].q;
+    mq.p[k] = Q[k].p;
+    mq.n[k] = h->dir[k].n;
+    mq.x[k] = Q[k].x;
+    mq.w[k] = Q[k].w;
+    mq.v[k] = Q[k].v;
+    for (int s : Q[k].span) mq.first[k].push_back(s - Q[k].p - 1);
   }
-  if (npts > ((size_t)1 << 26)) {
-    set_error("mapped domain too large for the host assembly of its spatial factors (quadrature points > 2^26)");
-    return STLS_EINVAL;
-  }
-  // metric at every tensor point (colex, direction 1 fastest), weight folded in
-  std::vector<Metric> met(npts);
-  {
-    const int nth = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
-    std::vector<std::thread> pool;
-    for (int t = 0; t < nth; ++t)
-      pool.emplace_back([&, t]() {
-        for (size_t e = t; e < npts; e += nth) {
-          double eta[3];
-          double w = 1.0;
-          size_t rem = e;
-          for (int k = 0; k < d; ++k) {
-            const int i = (int)(rem % ncol[k]);
-            rem /= ncol[k];
-            eta[k] = Q[k].x[i];
-            w *= Q[k].w[i];
-          }
-          metric_at(geometry, d, eta, met[e]);
-          met[e].det *= w;  // quadrature weight x |det J|
-        }
-      });
-    for (auto& th : pool) th.join();
-  }
-  int S = 1;
-  for (int k = 0; k < d; ++k) S *= bwk[k];
-  h->stencil = S;
-  const int64_t ns = h->ns;
-  std::vector<double> Ms((size_t)S * ns, 0.0), Js((size_t)S * ns, 0.0), Ls((size_t)S * ns, 0.0);
-  // --- assembly by rows (test functions): every row is owned by one thread
-  {
-    const int nth = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
-    std::vector<std::thread> pool;
-    for (int t = 0; t < nth; ++t)
-      pool.emplace_back([&, t]() {
-        for (int64_t row = t; row < ns; row += nth) {
-          int ir[3] = {0, 0, 0};
-          {
-            int64_t rem = row;
-            for (int k = 0; k < d; ++k) {
-              ir[k] = (int)(rem % n[k]);
-              rem /= n[k];
-            }
-          }
-          // support spans per direction: spans s with s - p <= f <= s, f = ir + 1
-          std::vector<int> sp[3];
-          for (int k = 0; k < d; ++k) {
-            const int f = ir[k] + 1, p = Q[k].p;
-            for (int e = 0; e < (int)Q[k].span.size(); ++e)
-              if (Q[k].span[e] - p <= f && f <= Q[k].span[e]) sp[k].push_back(e);
-          }
-          // loop over the support's points
-          int ce[3] = {0, 0, 0}, cg[3] = {0, 0, 0};
-          const int ne0 = (int)sp[0].size(), ne1 = d > 1 ? (int)sp[1].size() : 1, ne2 = d > 2 ? (int)sp[2].size() : 1;
-          for (ce[2] = 0; ce[2] < ne2; ++ce[2])
-            for (ce[1] = 0; ce[1] < ne1; ++ce[1])
-              for (ce[0] = 0; ce[0] < ne0; ++ce[0]) {
-                int el[3] = {0, 0, 0};
-                for (int k = 0; k < d; ++k) el[k] = sp[k][ce[k]];
-                const int q0 = Q[0].q, q1 = d > 1 ? Q[1].q : 1, q2 = d > 2 ? Q[2].q : 1;
-                for (cg[2] = 0; cg[2] < q2; ++cg[2])
-                  for (cg[1] = 0; cg[1] < q1; ++cg[1])
-                    for (cg[0] = 0; cg[0] < q0; ++cg[0]) {
-                      // 1-D data of this point per direction: values of the
-                      // span's functions and the position of the row's function
-                      const double* v1[3];
-                      int rpos[3];
-                      size_t pidx = 0, stride = 1;
-                      for (int k = 0; k < d; ++k) {
-                        const int pi = el[k] * Q[k].q + cg[k];
-                        v1[k] = &Q[k].v[(size_t)pi * 3 * (Q[k].p + 1)];
-                        rpos[k] = ir[k] + 1 - (Q[k].span[el[k]] - Q[k].p);
-                        pidx += (size_t)pi * stride;
-                        stride *= (size_t)ncol[k];
-                      }
-                      const Metric& mt = met[pidx];
-                      // test function: value, gradient, second derivatives
-                      auto val = [&](const int* c, int da, int db, double* out_v) {
-                        // derivative orders per direction from (da, db): -1 = none
-                        double prod = 1.0;
-                        for (int k = 0; k < d; ++k) {
-                          const int ord = (k == da) + (k == db);
-                          prod *= v1[k][ord * (Q[k].p + 1) + c[k]];
-                        }
-                        *out_v = prod;
-                      };
-                      double Bt, gt[3], Ht[3][3];
-                      val(rpos, -1, -1, &Bt);
-                      for (int a = 0; a < d; ++a) val(rpos, a, -1, &gt[a]);
-                      double lapt = 0.0;
-                      for (int a = 0; a < d; ++a)
-                        for (int b = 0; b < d; ++b) {
-                          val(rpos, a, b, &Ht[a][b]);
-                          lapt += mt.g[a][b] * Ht[a][b];
-                        }
-                      for (int a = 0; a < d; ++a) lapt += mt.lap[a] * gt[a];
-                      const double W = mt.det;
-                      // trial functions of this point's span
-                      int c[3] = {0, 0, 0};
-                      const int pc0 = Q[0].p + 1, pc1 = d > 1 ? Q[1].p + 1 : 1, pc2 = d > 2 ? Q[2].p + 1 : 1;
-                      for (c[2] = 0; c[2] < pc2; ++c[2])
-                        for (c[1] = 0; c[1] < pc1; ++c[1])
-                          for (c[0] = 0; c[0] < pc0; ++c[0]) {
-                            int o = 0, ostride = 1;
-                            bool ok = true;
-                            for (int k = 0; k < d; ++k) {
-                              const int jr = Q[k].span[el[k]] - Q[k].p + c[k] - 1;  // restricted column
-                              if (jr < 0 || jr >= n[k]) { ok = false; break; }
-                              o += (jr - ir[k] + Q[k].p) * ostride;
-                              ostride *= bwk[k];
-                            }
-                            if (!ok) continue;
-                            double Bc, gc[3];
-                            val(c, -1, -1, &Bc);
-                            for (int a = 0; a < d; ++a) val(c, a, -1, &gc[a]);
-                            double lapc = 0.0, gg = 0.0;
-                            for (int a = 0; a < d; ++a)
-                              for (int b = 0; b < d; ++b) {
-                                double hcb;
-                                val(c, a, b, &hcb);
-                                lapc += mt.g[a][b] * hcb;
-                                gg += mt.g[a][b] * gt[a] * gc[b];
-                              }
-                            for (int a = 0; a < d; ++a) lapc += mt.lap[a] * gc[a];
-                            const size_t at = (size_t)o * ns + (size_t)row;
-                            Ms[at] += W * Bt * Bc;
-                            Ls[at] += W * gg;
-                            Js[at] += W * lapt * lapc;
-                          }
-                    }
-              }
-        }
-      });
-    for (auto& th : pool) th.join();
-  }
-  // centre entries: the diagonals of M_s, J_s, L_s
-  int centre = 0;
-  {
-    int stride = 1;
-    for (int k = 0; k < d; ++k) {
-      centre += h->dir[k].p * stride;
-      stride *= bwk[k];
-    }
-  }
-  for (int f = 0; f < 3; ++f) h->sdiag[f].assign((size_t)ns, 0.0);
-  for (int64_t i = 0; i < ns; ++i) {
-    h->sdiag[0][(size_t)i] = Ms[(size_t)centre * ns + (size_t)i];
-    h->sdiag[1][(size_t)i] = Js[(size_t)centre * ns + (size_t)i];
-    h->sdiag[2][(size_t)i] = Ls[(size_t)centre * ns + (size_t)i];
-  }
-  h->hsten[0].swap(Ms);
-  h->hsten[1].swap(Js);
-  h->hsten[2].swap(Ls);
+  const int st = mapped_assemble(h, mq);
+  if (st) return st;
   // --- FD factors
   const Dir& Dt = h->dir[d];
   if (prec == 1) {
@@ -554,18 +301,7 @@ int mapped_update_sigma(stls_ctx* h) {
   return e == hipSuccess ? STLS_OK : hip_fail(e, "upload of the P^G scaling");
 }
 
-// Device copies of the stencils (the host copies are released).
-int mapped_upload(stls_ctx* h) {
-  for (int f = 0; f < 3; ++f) {
-    const size_t bytes = sizeof(double) * h->hsten[f].size();
-    hipError_t e = hipMalloc((void**)&h->sten[f], std::max<size_t>(bytes, 8));
-    if (e != hipSuccess) { set_error("hipMalloc (mapped-domain stencils)"); return STLS_ENOMEM; }
-    e = hipMemcpyAsync(h->sten[f], h->hsten[f].data(), bytes, hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(e, "upload of the mapped-domain stencils");
-    std::vector<double>().swap(h->hsten[f]);
-  }
-  return mapped_update_sigma(h);
-}
+// Last step of the mapped setup, after the workspaces: the P^G scaling.
+int mapped_upload(stls_ctx* h) { return mapped_update_sigma(h); }
 
 }  // namespace stls

@@ -149,8 +149,8 @@ struct stls_ctx {
   int stencil = 0;                // entries per stencil row: prod_k (2 p_k + 1)
   double* sten[3] = {nullptr, nullptr, nullptr};  // M_s, J_s, L_s as [stencil][ns] (device)
   double* sigma = nullptr;        // (P^G) sigma_i = (Pbar_ii / A_ii)^(1/2), ndof (device)
+  double* mapped_lx = nullptr;    // L_s x(:, final slice) inside the mapped matvec, ns (device)
   std::vector<double> sdiag[3];   // diagonals of M_s, J_s, L_s (host, ns)
-  std::vector<double> hsten[3];   // host stencils between assembly and upload
   std::vector<double> wdiag[stls::kMaxDim + 1][2];  // diagonals of the FD factors: space [M, J], time [K, M]
   stls::PcgScalars* scal = nullptr;
   stls::PcgScalars* scal_host = nullptr;  // pinned, 2 slots (convergence checks of alternate iterations)
@@ -201,11 +201,26 @@ int prec_apply_five_pass(stls_ctx* h, const double* r, double* s, const double* 
                          int* nparts, bool scale);
 int upload_diff_bands(stls_ctx* h);
 int ensure_diff_operands(stls_ctx* h);
-// Mapped domains (stls_geometry.cpp): host assembly of the pulled-back
-// spatial stencils, the geometry-weighted FD factors (replacing dir[k].U and
-// lam when the preconditioner is P^G) and the scaling vector; device side
-// in stls_mapped.hip.
+// Mapped domains (stls_geometry.cpp): quadrature data of the pulled-back
+// spatial factors, the geometry-weighted FD factors (replacing dir[k].U and
+// lam when the preconditioner is P^G) and the scaling vector; the stencils
+// are assembled on the device (stls_mapped.hip).
 int mapped_host_setup(stls_ctx* h, int geometry, int prec);
+// Gauss points of the non-empty spans of the space directions (host arrays,
+// span-major): per direction nel spans of q points, the points x, the
+// weights w, the values and first two derivatives of the span's p + 1
+// functions v[point][3][p+1], and per span the restricted index of its first
+// function (span - p - 1, negative where the span's first functions are the
+// dropped boundary ones).
+struct MappedQuad {
+  int d = 0, geom = 0;
+  int nel[kMaxDim] = {1, 1, 1}, q[kMaxDim] = {1, 1, 1}, p[kMaxDim] = {0, 0, 0}, n[kMaxDim] = {1, 1, 1};
+  std::vector<double> x[kMaxDim], w[kMaxDim], v[kMaxDim];
+  std::vector<int> first[kMaxDim];
+};
+// Allocates h->sten[0..2] (M_s, J_s, L_s as [stencil][ns]), assembles them
+// element by element and copies their diagonals into h->sdiag.
+int mapped_assemble(stls_ctx* h, const MappedQuad& mq);
 int mapped_upload(stls_ctx* h);
 int mapped_update_sigma(stls_ctx* h);
 int launch_mapped_matvec(stls_ctx* h, const double* x, double* y, const double* dot_with, double* partials,
