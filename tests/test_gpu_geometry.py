@@ -87,6 +87,37 @@ def test_mapped_pcg(d, nel, p, kappa, geometry):
     assert rel_err(to_host(x), x_ref) < 2 * d * 10 * 1e-10
 
 
+# Uneven sizes and degrees per direction (time last): row blocks of 32 and of
+# 16 rows along direction 1 with several blocks and ragged edges in every
+# direction, direction-1 stencil widths 5 and 7 (unrolled line loops) and 11
+# (the generic offset loop), mixed degrees, several chunks of time slices.
+SHAPES = [
+    (3, (20, 6, 9, 12), (2, 2, 2, 2)),   # n_1 = 20: 32-row blocks
+    (3, (36, 5, 6, 10), (2, 2, 2, 2)),   # n_1 = 36: 16-row blocks
+    (3, (10, 4, 3, 5), (3, 2, 2, 2)),    # width 7 along direction 1, mixed degrees
+    (3, (6, 3, 3, 3), (5, 2, 2, 2)),     # width 11: generic loop
+    (2, (30, 5, 4), (2, 2, 2)),          # 2-D, 32-row blocks
+    (2, (40, 5, 6), (2, 3, 2)),          # 2-D, 16-row blocks, mixed degrees
+]
+
+
+@pytest.mark.parametrize("d,nel,p", SHAPES, ids=[f"d{s[0]}-{'x'.join(map(str, s[1]))}-p{''.join(map(str, s[2]))}"
+                                                 for s in SHAPES])
+def test_mapped_block_shapes(d, nel, p):
+    assert stls is not None, "libstls.so is not built; run python paper_1809_10026_amd/build.py"
+    knots, degs = problem_knots(d, nel, p)
+    S = stls.Solver(knots, degs, geometry=_geom(d), prec=stls.STLS_PREC_GEOMETRY)
+    MP = geo.MappedProblem(_map(d), knots, degs)
+    assert S.ndof == MP.ndof
+    x = uniform_pm1(MP.ndof, 307)
+    assert rel_err(to_host(S.matvec(to_dev(x))), MP.matvec(x)) < 1e-13
+    pre = geo.GeometryPreconditioner(MP)
+    ref = pre.apply(x)
+    spread = max(l.max() / l.min() for l, _ in pre.fd.eig_space + [pre.fd.eig_time])
+    err = rel_err(to_host(S.prec_apply(to_dev(x))), ref)
+    assert err < max(1e-12, 4 * np.finfo(float).eps * spread), err
+
+
 def test_kappa_change_rescales_pg():
     S, MP = _pair(2, 7, 3, 1.0, 1)
     S.set_kappa(2.5)
