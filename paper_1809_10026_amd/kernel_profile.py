@@ -17,6 +17,13 @@ kappa log-uniform on [0.1, 10], right-hand sides U[-1, 1] with seeds
 20180927 + i, rtol 1e-8, FP64 FD), solved ``--solves`` times:
 
     rocprofv3 --kernel-trace --stats -d OUT -o run -- python3 -m paper_1809_10026_amd.kernel_profile --batch
+
+With ``--mapped`` it is the rotated quarter annulus of Table 2 at n_sub = 32,
+p = 2 (ndof 1,081,344): setup (stencil assembly on the device) and
+``--solves`` PCG solves to 1e-8 with P^G and FP64 FD, right-hand side
+U[-1, 1] (seed 1):
+
+    rocprofv3 --kernel-trace --stats -d OUT -o run -- python3 -m paper_1809_10026_amd.kernel_profile --mapped
 """
 from __future__ import annotations
 
@@ -34,6 +41,7 @@ def main():
     ap.add_argument("--solves", type=int, default=2)
     ap.add_argument("--mode", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--batch", action="store_true", help="the 256-problem batched solve instead")
+    ap.add_argument("--mapped", action="store_true", help="the rotated quarter annulus with P^G instead")
     args = ap.parse_args()
     import torch
 
@@ -42,6 +50,8 @@ def main():
 
     if args.batch:
         return batch(stls, torch, args.solves)
+    if args.mapped:
+        return mapped(stls, torch, args.solves)
 
     src = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
@@ -75,6 +85,18 @@ def batch(stls, torch, solves):
         _, its, rels = B.solve(b, 1e-8, 500)
         torch.cuda.synchronize()
         print(f"[kernel_profile] batch solve {i}: {max(its)} iterations, max relres {max(rels):.2e}", flush=True)
+
+
+def mapped(stls, torch, solves, n_sub=32, p=2):
+    from stls_inputs import problem_knots, uniform_pm1
+    knots, degs = problem_knots(3, n_sub, p)
+    S = stls.Solver(knots, degs, geometry=stls.STLS_GEOM_ROTATED_QUARTER_ANNULUS, prec=stls.STLS_PREC_GEOMETRY)
+    b = torch.as_tensor(uniform_pm1(S.ndof, 1)).cuda()
+    x = torch.empty_like(b)
+    for i in range(solves):
+        _, it, rel = S.solve(b, 1e-8, 3000, out=x)
+        torch.cuda.synchronize()
+        print(f"[kernel_profile] mapped solve {i}: {it} iterations, relres {rel:.2e}", flush=True)
 
 
 if __name__ == "__main__":

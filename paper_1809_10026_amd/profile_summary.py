@@ -35,6 +35,8 @@ CLASSES = [
     ("fd_mode_bf16x3_kernel", None), ("fd_mode_kernel", None),
     ("update_xr_kernel", "vec"), ("update_p_kernel", "vec"), ("dot_kernel", "vec"),
     ("finalize_kernel", "reduce"),
+    ("mapped_space_kernel", "mv_mapped_space"), ("mapped_time_kernel", "mv_mapped_time"),
+    ("mapped_scale_kernel", "vec"), ("mapped_assemble_kernel", "setup"),
 ]
 
 
