@@ -13,7 +13,10 @@ FP64 backward products, on MFMA inside the FP64 PCG); the FP64-plain solve, per-
 fractions, the matvec rate, errors against the FP64 oracle's own solution,
 the roofline of the dominant kernel (HIP-event durations measured on the
 solver's stream) and the oracle timed on the host cores are printed in the
-same JSON line.
+same JSON line.  Beside it, each with the oracle timed on the host: the
+diagonally scaled preconditioner, GPU error norms, the batched solve,
+lifting, the mapped domain (Table 2's rotated quarter annulus, P and P^G,
+the mapped matvec's roofline) and the adjoint gradient of the misfit.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -260,6 +263,8 @@ def main():
                             err_vs_fp64_solution=float(torch.linalg.norm(x - sol["fp64"]) / torch.linalg.norm(sol["fp64"])),
                             fd_prec_dof_per_s=N / fd_rate(modes[name]))
         log(f"{name} scaled: solve {dt*1e3:.3f} ms, {it} its, true {scaled[name]['true_relres']:.2e}")
+    S.set_fd_precision(modes["fp64"])
+    scaled_apply = S.prec_apply(b).cpu().numpy()  # for the oracle's scaled FD apply beside it
     S.set_fd_scaling(False)
 
     kernels = {m: kernel_table(res[m]["prof"], m, N) for m in modes}
@@ -278,6 +283,7 @@ def main():
     batch = gpu_batch(stls, torch)
     lifting = gpu_lifting(stls, torch, knots, degs)
     geometry = gpu_geometry(stls, torch)
+    gradient = gpu_gradient(stls, torch)
 
     cpu = None
     err_vs_oracle = None
@@ -293,7 +299,13 @@ def main():
         err_norms["oracle_cpu"] = cpu_error_norms()
         lifting["oracle_cpu"] = cpu_lifting(knots, degs)
         geometry["oracle_cpu"] = cpu_mapped_geometry(geometry)
+        gradient["oracle_cpu"] = cpu_gradient(gradient)
+        batch["oracle_cpu"] = cpu_batch(batch)
+        scaled["oracle_cpu"] = cpu_scaled_apply(knots, degs, b.cpu().numpy(), scaled_apply, scaled)
     geometry.get("small", {}).pop("solution", None)
+    batch.pop("sample", None)
+    for key in ("grad_f", "grad_kappa"):
+        gradient.pop(key, None)
 
     t_mixed, t_fp64 = res[mixed]["time_s"], res["fp64"]["time_s"]
     out = {
@@ -328,6 +340,7 @@ def main():
         "batch": batch,
         "lifting": lifting,
         "mapped_domain": geometry,
+        "gradient": gradient,
         "setup_s": setup_s,
         "roofline": roofline,
         "roofline_note": "kernel durations from HIP events recorded around every launch on the solver's "
@@ -410,13 +423,68 @@ def gpu_batch(stls, torch, steps=3):
     dt, its, rels = timed()
     log(f"batch: {dt*1e3:.1f} ms tuned ({dt_default*1e3:.1f} ms default shapes) for {B.total} unknowns, "
         f"{max(its)} iterations; tuning {B.tuning}")
+    nsamp = 8
     return {"workload": "256 independent d=2 problems, n_el per direction U{16..96}, p U{2..5}, "
                         "kappa 10^U(-1,1), RHS U[-1,1] (seeds 20180927+i), rtol 1e-8, FP64 FD",
+            "sample": {"problems": nsamp, "offsets": [int(v) for v in off[:nsamp + 1]],
+                       "x": x[:int(off[nsamp])].cpu().numpy(), "iters": [int(v) for v in its[:nsamp]]},
             "total_dof": int(B.total), "seconds": dt, "dof_per_s": B.total / dt, "max_iters": int(max(its)),
             "iteration_ms": dt / max(its) * 1e3, "graph_replay": bool(B.graph_used), "setup_s": setup_s,
             "max_relres": float(max(rels)),
             "autotune": {"seconds": tune_s, "tuning": B.tuning, "default_tuning": default_tuning,
                          "default_seconds": dt_default}}
+
+
+def cpu_scaled_apply(knots, degs, b, gpu_apply, scaled):
+    """The oracle's diagonally scaled FD apply (ScaledFD, FP64, host cores)
+    on the benchmark's right-hand side, and the error of the GPU's FP64
+    scaled apply of the same vector."""
+    import numpy as np
+
+    from oracle import fd, system
+    P = system.Problem(knots, degs)
+    t0 = time.perf_counter()
+    SF = fd.ScaledFD(P)
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    z = system.vec(SF.apply(b))
+    dt = time.perf_counter() - t0
+    err = float(np.linalg.norm(gpu_apply - z) / np.linalg.norm(z))
+    gpu_s = P.ndof / scaled["fp64"]["fd_prec_dof_per_s"]
+    log(f"cpu scaled FD apply: {dt:.2f} s (GPU FP64 {gpu_s*1e6:.0f} us); GPU vs oracle {err:.2e}")
+    return {"kind": "oracle", "sample": "one FP64 scaled FD apply of the benchmark right-hand side", "seconds": dt,
+            "setup_s": setup, "dof_per_s": P.ndof / dt, "gpu_fp64_vs_oracle_rel_l2": err}
+
+
+def cpu_batch(batch):
+    """The oracle's FD-PCG (FP64, host cores) on the first problems of the
+    batch, one after the other: time, rate, and the error of the GPU batch's
+    solutions of the same problems."""
+    import numpy as np
+
+    from oracle import fd, pcg, system
+    from stls_inputs import batch_params, batch_problem_knots, uniform_pm1
+    smp = batch.pop("sample")
+    nel, p, kappa = batch_params()
+    off = smp["offsets"]
+    errs, iters, dt = [], [], 0.0
+    for i in range(smp["problems"]):
+        knots, degs = batch_problem_knots(nel[i], p[i])
+        t0 = time.perf_counter()
+        P = system.Problem(knots, degs, float(kappa[i]))
+        F = fd.FD(P)
+        b = uniform_pm1(off[i + 1] - off[i], 20180927 + i)
+        xo, info = pcg.pcg(lambda v: system.vec(P.matvec(v)), lambda v: system.vec(F.apply(v)), b, 1e-8, maxit=500)
+        dt += time.perf_counter() - t0
+        xg = smp["x"][off[i]:off[i + 1]]
+        errs.append(float(np.linalg.norm(xg - xo) / np.linalg.norm(xo)))
+        iters.append(int(info["iters"]))
+    log(f"cpu batch sample: {smp['problems']} problems, {off[-1]} unknowns in {dt:.2f} s; GPU solutions vs oracle "
+        f"max {max(errs):.2e}; iterations GPU {smp['iters']} oracle {iters}")
+    return {"kind": "oracle", "sample": f"problems 0..{smp['problems'] - 1} of the batch, solved one after the other "
+                                        "(setup included)", "unknowns": int(off[-1]), "seconds": dt,
+            "dof_per_s": off[-1] / dt, "gpu_vs_oracle_max_rel_l2": max(errs), "iters_oracle": iters,
+            "iters_gpu": smp["iters"]}
 
 
 def gpu_geometry(stls, torch, n_sub=32, p=2, reps=3, mv_reps=50, small=12):
@@ -522,6 +590,79 @@ def cpu_mapped_geometry(geometry, p=2):
     return {"kind": "oracle", "workload": f"rotated quarter annulus, n_sub={small['n_sub']}, p={p}, P^G, rtol 1e-8",
             "ndof": MP.ndof, "iters": info["iters"], "seconds": dt, "setup_s": setup,
             "gpu_seconds": small["seconds"], "gpu_iters": small["iters"], "gpu_vs_oracle_rel_l2": err}
+
+
+def gpu_gradient(stls, torch, reps=3, rtol=1e-8):
+    """Adjoint gradient of the space-time misfit (cfg 5): d = 2, p = 3, 128
+    elements per direction (ndof 2,163,330; forcing coefficients 131^3 in the
+    full spline space), kappa = 1, forcing U[-1, 1] (seed 5), target u* the
+    solution for a second forcing (seed 6).  One evaluation = load operator,
+    PCG solve, misfit with its gradient, adjoint PCG solve, B^T and the kappa
+    derivative (autograd.HeatSolve / Misfit), FP64 FD, solves to 1e-8."""
+    from paper_1809_10026_amd import autograd as sag
+    from stls_inputs import problem_knots, uniform_pm1
+    knots, degs = problem_knots(2, 128, 3)
+    S = stls.Solver(knots, degs, kappa=1.0)
+    _, nf = S.forcing_shape
+    fstar = torch.as_tensor(uniform_pm1(nf, 6)).cuda()
+    F = S.load_apply(fstar)
+    ustar, _, _ = S.solve(F, rtol=rtol)
+    f0 = torch.as_tensor(uniform_pm1(nf, 5)).cuda()
+
+    def evaluate():
+        f = f0.clone().requires_grad_(True)
+        kt = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+        L = sag.misfit(sag.heat_solve(f, kt, S, rtol=rtol), ustar, S)
+        L.backward()
+        return float(L), f.grad, float(kt.grad)
+
+    evaluate()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        L, gf, gk = evaluate()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    log(f"gradient (cfg 5): loss {L:.6e}, dL/dkappa {gk:.6e}, {dt*1e3:.2f} ms per evaluation")
+    out = {"workload": "d=2, p=3, 128 elements/dir (ndof 2,163,330, forcing 131^3), kappa 1, f U[-1,1] seed 5, "
+                       "target u* from seed 6, FP64 FD, PCG rtol 1e-8: loss and its gradient in f and kappa",
+           "ndof": S.ndof, "forcing_size": nf, "seconds": dt, "loss": L, "dL_dkappa": gk,
+           "solves_per_evaluation": 2, "grad_f": gf.cpu().numpy(), "grad_kappa": gk}
+    S.close()
+    return out
+
+
+def cpu_gradient(gradient):
+    """The oracle's loss and gradient on the host cores (oracle FD-PCG as the
+    solver, its own target solve), and the error of the GPU's gradient."""
+    import numpy as np
+
+    from oracle import fd, grad as ograd, pcg, system
+    from stls_inputs import problem_knots, uniform_pm1
+    knots, degs = problem_knots(2, 128, 3)
+    t0 = time.perf_counter()
+    P = system.Problem(knots, degs)
+    Fd = fd.FD(P)
+    G = ograd.Misfit(P)
+    setup = time.perf_counter() - t0
+
+    def solve(b):
+        return np.asarray(pcg.pcg(lambda v: system.vec(P.matvec(v)), lambda v: system.vec(Fd.apply(v)), b, 1e-8,
+                                  maxit=300)[0])
+
+    m = [len(k) - q - 1 for k, q in zip(knots, degs)]
+    nf = int(np.prod(m))
+    ustar = solve(G.load_apply(uniform_pm1(nf, 6).reshape(m, order="F")).ravel(order="F"))
+    t0 = time.perf_counter()
+    L, gf, dk, _ = G.loss_and_grad(uniform_pm1(nf, 5).reshape(m, order="F"), ustar, solve)
+    dt = time.perf_counter() - t0
+    gfo = np.asarray(gf).ravel(order="F")
+    err_f = float(np.linalg.norm(gradient["grad_f"] - gfo) / np.linalg.norm(gfo))
+    err_k = float(abs(gradient["grad_kappa"] - dk) / abs(dk))
+    log(f"cpu gradient: {dt:.2f} s per evaluation (setup {setup:.1f} s); GPU vs oracle: dL/df {err_f:.2e}, "
+        f"dL/dkappa {err_k:.2e}")
+    return {"kind": "oracle", "seconds": dt, "setup_s": setup, "loss": L, "dL_dkappa": dk,
+            "gpu_vs_oracle_grad_f_rel_l2": err_f, "gpu_vs_oracle_grad_kappa_rel": err_k}
 
 
 def gpu_lifting(stls, torch, knots, degs, reps=20):
