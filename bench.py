@@ -624,10 +624,20 @@ def gpu_gradient(stls, torch, reps=3, rtol=1e-8):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t) / reps
     log(f"gradient (cfg 5): loss {L:.6e}, dL/dkappa {gk:.6e}, {dt*1e3:.2f} ms per evaluation")
+    # one more evaluation with HIP events around every launch: time per kernel class
+    stls.stls_set_profiling(S.handle, True)
+    stls.stls_profile_reset(S.handle)
+    evaluate()
+    torch.cuda.synchronize()
+    split = {k: round(v[1], 3) for k, v in stls.stls_profile(S.handle).items() if v[0]}
+    stls.stls_set_profiling(S.handle, False)
     out = {"workload": "d=2, p=3, 128 elements/dir (ndof 2,163,330, forcing 131^3), kappa 1, f U[-1,1] seed 5, "
                        "target u* from seed 6, FP64 FD, PCG rtol 1e-8: loss and its gradient in f and kappa",
            "ndof": S.ndof, "forcing_size": nf, "seconds": dt, "loss": L, "dL_dkappa": gk,
-           "solves_per_evaluation": 2, "grad_f": gf.cpu().numpy(), "grad_kappa": gk}
+           "solves_per_evaluation": 2, "ms_per_kernel_class": split,
+           "note": "diff = the band products of the load operator, its transpose and the kappa derivative "
+                   "(generic banded mode-product kernel); the rest is the two PCG solves",
+           "grad_f": gf.cpu().numpy(), "grad_kappa": gk}
     S.close()
     return out
 

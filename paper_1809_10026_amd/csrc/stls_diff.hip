@@ -61,6 +61,98 @@ __global__ __launch_bounds__(kT) void band_rect_kernel(const double* __restrict_
   }
 }
 
+// One mode of the general lifting's class recurrence (see stls_lift_apply),
+// over the (L, n_in, R) view of the four class arrays M, J, H, G:
+//   FIRST (from u_B alone): M' = B0 u, J' = B1 u, H' = B2 u, G' = B3 u
+//   MID:   M' = B0 M, J' = B0 J + B1 M + B3 H + B2 G, H' = B0 H + B2 M,
+//          G' = B0 G + B3 M                 (B0..B3 = Mbar, Jbar, Hbar, Gbar)
+//   TIME:  F += c0 B0 M + c1 B1 J + c2 B2 G + c3 B3 H
+//                                           (B0..B3 = Kbar_t, Mbar_t, Dbar_t, Cbar_t)
+// Rectangular bands (restricted rows x full columns, offset 1), staged in
+// LDS; the four bands' taps are shared by every class that uses them.
+constexpr int kCls = 4;
+enum { kLiftFirst = 0, kLiftMid = 1, kLiftTime = 2 };
+// output rows per thread: 4 where four class arrays are read (their taps
+// shared by the run), 1 for the first mode (one input)
+template <int MODE>
+constexpr int lift_rows() { return MODE == kLiftFirst ? 1 : 4; }
+
+struct LiftPass {
+  const double* in[kCls];
+  double* out[kCls];
+  const double* band[kCls];
+  double coef[kCls];
+  int L, n_in, n_out, R, p;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(kT) void lift_class_kernel(LiftPass a) {
+  constexpr int kLiftRows = lift_rows<MODE>();
+  extern __shared__ double bs[];  // [4][n_out * bw]
+  const int p = a.p, bw = 2 * p + 1, nb = a.n_out * bw;
+  for (int q = threadIdx.x; q < kCls * nb; q += kT) bs[q] = a.band[q / nb][q % nb];
+  __syncthreads();
+  // one thread per (l, run of kLiftRows consecutive rows i, r): the runs'
+  // overlapping taps are loaded once
+  const unsigned L = (unsigned)a.L, n_out = (unsigned)a.n_out;
+  const unsigned nrun = (n_out + kLiftRows - 1) / kLiftRows;
+  const unsigned total = L * nrun * (unsigned)a.R;
+  for (unsigned w = blockIdx.x * kT + threadIdx.x; w < total; w += gridDim.x * kT) {
+    const unsigned l = w % L, rest = w / L;
+    const int i0 = (int)(rest % nrun) * kLiftRows;
+    const unsigned r = rest / nrun;
+    const size_t base = (size_t)l + (size_t)r * L * (unsigned)a.n_in;
+    const int jlo = max(0, i0 + 1 - p), jhi = min(a.n_in - 1, i0 + kLiftRows + p);
+    double oM[kLiftRows], oJ[kLiftRows], oH[kLiftRows], oG[kLiftRows];
+#pragma unroll
+    for (int u = 0; u < kLiftRows; ++u) oM[u] = oJ[u] = oH[u] = oG[u] = 0.0;
+    for (int j = jlo; j <= jhi; ++j) {
+      const size_t g = base + (size_t)j * L;
+      const double vM = a.in[0][g];
+      double vJ = 0.0, vH = 0.0, vG = 0.0;
+      if constexpr (MODE != kLiftFirst) {
+        vJ = a.in[1][g];
+        vH = a.in[2][g];
+        vG = a.in[3][g];
+      }
+#pragma unroll
+      for (int u = 0; u < kLiftRows; ++u) {
+        const int i = i0 + u, o = j - i - 1 + p;  // tap of row i, B(i, j) at i*bw + o
+        if (o < 0 || o > 2 * p || i >= a.n_out) continue;
+        const double* b0 = bs + i * bw + o;
+        const double c0 = b0[0], c1 = b0[nb], c2 = b0[2 * nb], c3 = b0[3 * nb];
+        if constexpr (MODE == kLiftFirst) {
+          oM[u] += c0 * vM;
+          oJ[u] += c1 * vM;
+          oH[u] += c2 * vM;
+          oG[u] += c3 * vM;
+        } else if constexpr (MODE == kLiftMid) {
+          oM[u] += c0 * vM;
+          oJ[u] += c0 * vJ + c1 * vM + c3 * vH + c2 * vG;
+          oH[u] += c0 * vH + c2 * vM;
+          oG[u] += c0 * vG + c3 * vM;
+        } else {
+          oM[u] += a.coef[0] * c0 * vM + a.coef[1] * c1 * vJ + a.coef[2] * c2 * vG + a.coef[3] * c3 * vH;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kLiftRows; ++u) {
+      const int i = i0 + u;
+      if (i >= a.n_out) break;
+      const size_t e = (size_t)l + (size_t)L * ((size_t)i + (size_t)n_out * r);
+      if constexpr (MODE == kLiftTime) {
+        a.out[0][e] += oM[u];
+      } else {
+        a.out[0][e] = oM[u];
+        a.out[1][e] = oJ[u];
+        a.out[2][e] = oH[u];
+        a.out[3][e] = oG[u];
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kT) void sub_kernel(const double* __restrict__ a, const double* __restrict__ b,
                                                  double* __restrict__ c, long long n) {
   for (long long e = (long long)blockIdx.x * kT + threadIdx.x; e < n; e += (long long)gridDim.x * kT) c[e] = a[e] - b[e];
@@ -223,55 +315,6 @@ std::vector<std::pair<double, std::vector<Fac>>> lift_terms(stls_ctx* h) {
   return terms;
 }
 
-// Terms of a(u_B, B_i) for a lifting u_B anywhere in the full space
-// (boundary and/or initial coefficients), least-squares form of §3.2
-// assembled term by term: for such a trial function the integrations by
-// parts that give the system matrix leave boundary terms.  Factors are
-// restricted (test) rows x full (trial) columns.
-//   int int d_t u d_t v          : Kbar_t (x) Mbar_s
-//   kappa^2 int int Lap u Lap v  : Mbar_t (x) (Jbar_k, or Hbar_k Gbar_l for k != l)
-//   -kappa int int d_t u Lap v   : Dbar_t (x) Gbar_k
-//   -kappa int int Lap u d_t v   : Cbar_t (x) Hbar_k
-// (other modes Mbar; G: test function differentiated twice, H: trial).
-std::vector<std::pair<double, std::vector<Fac>>> general_lift_terms(stls_ctx* h) {
-  const int d = h->d;
-  const DevDir& T = h->dd[d];
-  auto R = [&](int k, const double* band) { return rect(h->dd[k], band); };
-  const double k2 = h->kappa * h->kappa, kap = h->kappa;
-  std::vector<std::pair<double, std::vector<Fac>>> terms;
-  std::vector<Fac> f0;
-  for (int k = 0; k < d; ++k) f0.push_back(R(k, h->dd[k].Mbar));
-  f0.push_back(R(d, T.Kbar));
-  terms.push_back({1.0, f0});
-  for (int k = 0; k < d; ++k)
-    for (int l = 0; l < d; ++l) {
-      std::vector<Fac> f;
-      for (int m = 0; m < d; ++m) {
-        const DevDir& D = h->dd[m];
-        const double* b = D.Mbar;
-        if (k == l && m == k) b = D.Jbar;
-        else if (m == k) b = D.Hbar;
-        else if (m == l) b = D.Gbar;
-        f.push_back(R(m, b));
-      }
-      f.push_back(R(d, T.Mbar));
-      terms.push_back({k2, f});
-    }
-  for (int k = 0; k < d; ++k) {
-    std::vector<Fac> f;
-    for (int m = 0; m < d; ++m) f.push_back(R(m, m == k ? h->dd[m].Gbar : h->dd[m].Mbar));
-    f.push_back(R(d, T.Dbar));
-    terms.push_back({-kap, f});
-  }
-  for (int k = 0; k < d; ++k) {
-    std::vector<Fac> f;
-    for (int m = 0; m < d; ++m) f.push_back(R(m, m == k ? h->dd[m].Hbar : h->dd[m].Mbar));
-    f.push_back(R(d, T.Cbar));
-    terms.push_back({-kap, f});
-  }
-  return terms;
-}
-
 // u[full index of r] += w[r] for every restricted multi-index r: space
 // index i is full index i + 1 (the first function is dropped), time too.
 struct EmbedShape {
@@ -426,12 +469,27 @@ int stls_lift_combine(stls_handle h, const double* u0, const double* x, double* 
   return e == hipSuccess ? STLS_OK : hip_fail(e, "hipMemcpyAsync");
 }
 
-// F -= sum over terms of c (F_t (x) F_{d-1} (x) ... (x) F_0) u_B, evaluated as
-// a depth-first walk over the terms' spatial factors: modes 0 .. d-2 reuse
-// the intermediate of every distinct prefix, the last spatial mode adds
-// c times its result into one full-time sum per time factor, and each sum
-// takes one time product into F.  (16 chains of 4 products at d = 3 become
-// 33 products.)
+// General lifting, F -= a(u_B, B_i), for a lifting u_B anywhere in the full
+// space (boundary and/or initial coefficients): least-squares form of §3.2
+// assembled term by term, since for such a trial function the integrations
+// by parts that give the system matrix leave boundary terms.  Factors are
+// restricted (test) rows x full (trial) columns:
+//   int int d_t u d_t v          : Kbar_t (x) Mbar_s
+//   kappa^2 int int Lap u Lap v  : Mbar_t (x) (Jbar_k, or Hbar_k Gbar_l for k != l)
+//   -kappa int int d_t u Lap v   : Dbar_t (x) Gbar_k
+//   -kappa int int Lap u d_t v   : Cbar_t (x) Hbar_k
+// (other modes Mbar; G: test function differentiated twice, H: trial;
+// 16 terms at d = 3), evaluated one mode at a time.  After the
+// space modes 0 .. m every partial product lies in one of four classes by
+// which special factors it has taken: none (M), the whole second-derivative
+// part, J_k or H_k with G_l (J), H only (H), G only (G).  A space mode maps
+// the classes as
+//   M' = Mbar M,  J' = Mbar J + Jbar M + Gbar H + Hbar G,
+//   H' = Mbar H + Hbar M,  G' = Mbar G + Gbar M,
+// starting from u_B in class M alone, and the time mode closes them:
+//   F -= Kbar_t M + kappa^2 Mbar_t J - kappa Dbar_t G - kappa Cbar_t H.
+// (At d = 3: 4 passes of lift_class_kernel in place of 16 chains of 4
+// products.)
 int stls_lift_apply(stls_handle h, const double* ub, double* F) {
   if (h && h->geometry) { set_error("stls_lift_apply: unit box only (not available on a mapped domain)"); return STLS_EINVAL; }
   if (!h || !ub || !F) { set_error("bad handle or pointers"); return STLS_EINVAL; }
@@ -439,65 +497,65 @@ int stls_lift_apply(stls_handle h, const double* ub, double* F) {
   if (st) return st;
   const int d = h->d;
   for (int g = 0; g < 4 && !st; ++g)
-    if (!h->lgrp[g] && hipMalloc((void**)&h->lgrp[g], sizeof(double) * (size_t)h->nfull) != hipSuccess) {
+    if ((!h->lgrp[g] && hipMalloc((void**)&h->lgrp[g], sizeof(double) * (size_t)h->nfull) != hipSuccess) ||
+        (!h->lcls[g] && hipMalloc((void**)&h->lcls[g], sizeof(double) * (size_t)h->nfull) != hipSuccess)) {
       set_error("hipMalloc lifting workspace");
       st = STLS_ENOMEM;
     }
   if (st) return st;
-  const auto terms = general_lift_terms(h);
-  std::vector<const double*> tband;  // distinct time factors, in order of first use
-  std::vector<int> tgroup(terms.size());
-  for (size_t i = 0; i < terms.size(); ++i) {
-    const double* b = terms[i].second[d].band;
-    size_t g = 0;
-    while (g < tband.size() && tband[g] != b) ++g;
-    if (g == tband.size()) tband.push_back(b);
-    tgroup[i] = (int)g;
-  }
-  if (tband.size() > 4) { set_error("lifting: unexpected number of time factors"); return STLS_EINVAL; }
-  std::vector<bool> started(tband.size(), false);
-  std::vector<int> cur0(d + 1);
-  for (int k = 0; k <= d; ++k) cur0[k] = h->dd[k].m;
-  // walk(level k, input tensor, its mode sizes, the terms that share the prefix)
-  std::function<int(int, const double*, std::vector<int>, const std::vector<int>&)> walk =
-      [&](int k, const double* in, std::vector<int> cur, const std::vector<int>& sub) -> int {
-    std::vector<const double*> seen;
-    for (int i : sub) {
-      const Fac& f = terms[i].second[k];
-      bool dup = false;
-      for (const double* b : seen) dup = dup || b == f.band;
-      if (dup) continue;
-      seen.push_back(f.band);
-      std::vector<int> next;
-      for (int j : sub)
-        if (terms[j].second[k].band == f.band) next.push_back(j);
-      std::vector<int> out = cur;
-      out[k] = f.n_out;
-      int s2;
-      if (k < d - 1) {
-        double* tmp = h->ftmp[k % 2];
-        if ((s2 = apply_mode(h, in, tmp, cur, k, f, 1.0, false))) return s2;
-        if ((s2 = walk(k + 1, tmp, out, next))) return s2;
-      } else {
-        for (int j : next) {
-          const int g = tgroup[j];
-          if ((s2 = apply_mode(h, in, h->lgrp[g], cur, k, f, terms[j].first, started[g]))) return s2;
-          started[g] = true;
-        }
+  std::vector<long long> cur(d + 1);
+  for (int k = 0; k <= d; ++k) cur[k] = h->dd[k].m;
+  long long full = 1;
+  for (int k = 0; k <= d; ++k) full *= cur[k];
+  if (full >= 0xffffffffLL - (long long)kMaxBlocks * kT) { set_error("lifting: too many entries"); return STLS_EINVAL; }
+  double* const* sets[2] = {h->lgrp, h->lcls};
+  const double* cls[kCls] = {ub, nullptr, nullptr, nullptr};
+  for (int m = 0; m <= d; ++m) {
+    const DevDir& D = h->dd[m];
+    LiftPass a = {};
+    long long L = 1, R = 1;
+    for (int q = 0; q < m; ++q) L *= cur[q];
+    for (int q = m + 1; q <= d; ++q) R *= cur[q];
+    a.L = (int)L;
+    a.R = (int)R;
+    a.n_in = D.m;
+    a.n_out = D.n;
+    a.p = D.p;
+    for (int k = 0; k < kCls; ++k) a.in[k] = cls[k];
+    const int mode = m == d ? kLiftTime : m == 0 ? kLiftFirst : kLiftMid;
+    if (mode == kLiftTime) {
+      const double k2 = h->kappa * h->kappa, kap = h->kappa;
+      const double* bands[kCls] = {D.Kbar, D.Mbar, D.Dbar, D.Cbar};
+      const double coef[kCls] = {-1.0, -k2, kap, kap};
+      for (int k = 0; k < kCls; ++k) {
+        a.band[k] = bands[k];
+        a.coef[k] = coef[k];
+      }
+      a.out[0] = F;
+    } else {
+      const double* bands[kCls] = {D.Mbar, D.Jbar, D.Hbar, D.Gbar};
+      for (int k = 0; k < kCls; ++k) {
+        a.band[k] = bands[k];
+        a.out[k] = sets[m % 2][k];
       }
     }
-    return STLS_OK;
-  };
-  std::vector<int> all(terms.size());
-  for (size_t i = 0; i < terms.size(); ++i) all[i] = (int)i;
-  if ((st = walk(0, ub, cur0, all))) return st;
-  std::vector<int> curt(d + 1);
-  for (int k = 0; k < d; ++k) curt[k] = h->dd[k].n;
-  curt[d] = h->dd[d].m;
-  for (size_t g = 0; g < tband.size(); ++g) {
-    if (!started[g]) continue;
-    const Fac ft = terms[std::find(tgroup.begin(), tgroup.end(), (int)g) - tgroup.begin()].second[d];
-    if ((st = apply_mode(h, h->lgrp[g], F, curt, d, ft, -1.0, true))) return st;
+    const size_t shmem = sizeof(double) * kCls * D.n * (2 * D.p + 1);
+    if (shmem > 160 * 1024) { set_error("lifting: bands too large for the pass's LDS"); return STLS_EINVAL; }
+    const int rows = mode == kLiftFirst ? lift_rows<kLiftFirst>() : lift_rows<kLiftMid>();
+    const long long total = L * ((a.n_out + rows - 1) / rows) * R;
+    auto kern = mode == kLiftFirst ? lift_class_kernel<kLiftFirst>
+                : mode == kLiftMid ? lift_class_kernel<kLiftMid> : lift_class_kernel<kLiftTime>;
+    if (shmem > 65536) {
+      const hipError_t ea = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+      if (ea != hipSuccess) return hip_fail(ea, "hipFuncSetAttribute(LDS)");
+    }
+    prof_begin(h);
+    hipLaunchKernelGGL(kern, dim3(grid_for(total)), dim3(kT), shmem, h->stream, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "lift_class_kernel launch");
+    prof_end(h, PROF_DIFF);
+    cur[m] = D.n;
+    for (int g = 0; g < kCls; ++g) cls[g] = sets[m % 2][g];
   }
   return STLS_OK;
 }

@@ -137,7 +137,8 @@ struct stls_ctx {
   double* partials = nullptr;
   double* dres = nullptr;          // device scalar result of stls_dot
   double* ftmp[2] = {nullptr, nullptr};  // full-space temporaries (differentiation ops)
-  double* lgrp[4] = {nullptr, nullptr, nullptr, nullptr};  // lifting: one full-space sum per time factor
+  double* lgrp[4] = {nullptr, nullptr, nullptr, nullptr};  // lifting: the four factor classes (one set)
+  double* lcls[4] = {nullptr, nullptr, nullptr, nullptr};  // lifting: the four factor classes (other set)
   int64_t nfull = 0;               // prod of full sizes m_k
   bool bands_ready = false;        // rectangular bands on the device (uploaded at setup)
   bool diff_ready = false;         // and the full-space temporaries allocated
