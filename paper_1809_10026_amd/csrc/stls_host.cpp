@@ -542,7 +542,7 @@ static void free_ctx(stls_ctx* h) {
   void* ptrs[] = {h->diag64, h->diag32, h->lam_s, h->lam_s_raw, h->work[0], h->work[1], h->work[2], h->work[3], h->work[4],
                   h->work[5], h->fdbuf[0], h->fdbuf[1], h->r, h->z, h->pvec, h->q, h->partials, h->scal,
                   h->dres, h->ftmp[0], h->ftmp[1], h->lgrp[0], h->lgrp[1], h->lgrp[2], h->lgrp[3], h->lcls[0], h->lcls[1], h->lcls[2], h->lcls[3],
-                  h->sten[0], h->sten[1], h->sten[2], h->sigma, h->mapped_lx};
+                  h->sten[0], h->sten[1], h->sten[2], h->sigma, h->mapped_lx, h->norm_ws};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (h->scal_host) (void)hipHostFree(h->scal_host);

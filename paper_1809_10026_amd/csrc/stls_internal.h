@@ -151,6 +151,8 @@ struct stls_ctx {
   double* sten[3] = {nullptr, nullptr, nullptr};  // M_s, J_s, L_s as [stencil][ns] (device)
   double* sigma = nullptr;        // (P^G) sigma_i = (Pbar_ii / A_ii)^(1/2), ndof (device)
   double* mapped_lx = nullptr;    // L_s x(:, final slice) inside the mapped matvec, ns (device)
+  char* norm_ws = nullptr;        // stls_error_norms: tables and temporaries (device)
+  size_t norm_ws_bytes = 0;
   std::vector<double> sdiag[3];   // diagonals of M_s, J_s, L_s (host, ns)
   std::vector<double> wdiag[stls::kMaxDim + 1][2];  // diagonals of the FD factors: space [M, J], time [K, M]
   stls::PcgScalars* scal = nullptr;

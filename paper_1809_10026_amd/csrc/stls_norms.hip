@@ -7,8 +7,9 @@
 //
 // The space directions are evaluated first (one chain per spatial derivative
 // pattern, kept as a (grid_s, n_t) tensor), then the time direction in chunks
-// of quadrature points, each chunk reduced at once; the device temporaries
-// are allocated for the call.
+// of quadrature points, each chunk evaluated inside the reduction that
+// compares it with the exact solution; the device temporaries live in a
+// per-handle workspace that grows when a call needs more.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,7 +25,7 @@ namespace {
 constexpr int kNT = 256;
 constexpr int kNormBlocks = 4096;
 constexpr int kMaxTerms = 64;
-constexpr long long kChunkPoints = 1LL << 26;  // grid points per time chunk (512 MB of FP64)
+constexpr long long kChunkPoints = 1LL << 26;  // grid points per time chunk (one reduction launch)
 
 // Quadrature grid of one direction and the basis values at its points.
 struct Grid1 {
@@ -116,21 +117,37 @@ __device__ inline double block_sum_n(double v, double* red) {
 }
 
 // partials[2b], partials[2b+1]: block b's sums of w (F - f)^2 and w f^2 over
-// the chunk F of shape (nq_1, ..., nq_d, chunk) (colex).
-__global__ __launch_bounds__(kNT) void err_reduce_kernel(const double* __restrict__ F, long long total, NormArgs A,
-                                                         double* __restrict__ partials) {
+// a chunk of time points, with F, the field on the grid, formed on the fly
+// from the space-evaluated S (shape (grid_s, n_t), grid_s = Gs):
+//   F(l, q) = sum_a Et[q0 + q][a] S(l, first_t[q0 + q] + a),
+// so the chunk never goes through memory.
+__global__ __launch_bounds__(kNT) void err_reduce_kernel(const double* __restrict__ S, long long Gs, int nt, int chunk,
+                                                         const double* __restrict__ Et, const int* __restrict__ first_t,
+                                                         int np, NormArgs A, double* __restrict__ partials) {
   __shared__ double red[kNT / 64];
   double se = 0.0, sr = 0.0;
+  const long long total = Gs * chunk;
   for (long long e = blockIdx.x * (long long)kNT + threadIdx.x; e < total; e += (long long)gridDim.x * kNT) {
+    const long long l = e % Gs;
+    const int qt = A.q0 + (int)(e / Gs);
+    double Fv = 0.0;
+    {
+      const int f0 = first_t[qt];
+      const double* row = Et + (size_t)qt * np;
+      for (int a = 0; a < np; ++a) {
+        const int j = f0 + a;
+        if (j >= 0 && j < nt) Fv += row[a] * S[l + (size_t)j * Gs];
+      }
+    }
     int idx[kMaxDim + 1];
-    long long rest = e;
+    long long rest = l;
 #pragma unroll
     for (int k = 0; k < kMaxDim; ++k) {
       if (k >= A.d) break;
       idx[k] = (int)(rest % A.nq[k]);
       rest /= A.nq[k];
     }
-    idx[A.d] = A.q0 + (int)rest;
+    idx[A.d] = qt;
     double wq = 1.0;
     for (int k = 0; k <= A.d; ++k) wq *= A.w[A.wbase[k] + idx[k]];
     double f = 0.0;
@@ -140,7 +157,7 @@ __global__ __launch_bounds__(kNT) void err_reduce_kernel(const double* __restric
         for (int k = 0; k <= A.d; ++k) prod *= A.g[A.gbase[k] + ((long long)s * 3 + A.pat[pt][k]) * A.nq[k] + idx[k]];
         f += prod;
       }
-    const double diff = F[e] - f;
+    const double diff = Fv - f;
     se += wq * diff * diff;
     sr += wq * f * f;
   }
@@ -154,32 +171,16 @@ __global__ __launch_bounds__(kNT) void err_reduce_kernel(const double* __restric
 
 int blocks_for(long long n) { return (int)std::max<long long>(1, std::min<long long>((n + kNT - 1) / kNT, kNormBlocks)); }
 
-template <typename T>
-int upload(T** dst, const std::vector<T>& v, hipStream_t st) {
-  if (hipMalloc((void**)dst, std::max<size_t>(v.size(), 1) * sizeof(T)) != hipSuccess) {
-    set_error("hipMalloc (error norms)");
-    return STLS_ENOMEM;
-  }
-  if (!v.empty() && hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess) {
-    set_error("hipMemcpyAsync (error norms)");
-    return STLS_EHIP;
-  }
-  return STLS_OK;
-}
-
-struct Scratch {
-  std::vector<void*> ptrs;
-  ~Scratch() {
-    for (void* p : ptrs) (void)hipFree(p);
-  }
+// Carves the call's device buffers out of the handle's norm workspace (kept
+// between calls, grown when a call needs more): 256-byte aligned pieces.
+struct Arena {
+  size_t used = 0;
+  char* base = nullptr;
   template <typename T>
-  int alloc(T** p, size_t count) {
-    if (hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
-      set_error("hipMalloc (error norms)");
-      return STLS_ENOMEM;
-    }
-    ptrs.push_back(*p);
-    return STLS_OK;
+  T* take(size_t count) {
+    T* p = reinterpret_cast<T*>(base ? base + used : nullptr);
+    used += (std::max<size_t>(count, 1) * sizeof(T) + 255) / 256 * 256;
+    return p;
   }
 };
 
@@ -212,20 +213,13 @@ int stls_error_norms(stls_handle h, const double* u, int nterms, const double* c
     for (int k = 0; k <= d; ++k)
       if (!g[s * (d + 1) + k]) { set_error("NULL exact-solution factor"); return STLS_EINVAL; }
   hipStream_t st = h->stream;
-  Scratch sc;
   int rc = STLS_OK;
-  // evaluation tables, weights and exact factors
-  double* dE[kMaxDim + 1];
-  int* dF[kMaxDim + 1];
+  // evaluation tables, weights and exact factors (host side)
   NormArgs A;
   A.d = d;
   A.nterms = nterms;
   std::vector<double> wall, gall;
   for (int k = 0; k <= d; ++k) {
-    if ((rc = upload(&dE[k], G[k].E, st))) return rc;
-    sc.ptrs.push_back(dE[k]);
-    if ((rc = upload(&dF[k], G[k].first, st))) return rc;
-    sc.ptrs.push_back(dF[k]);
     A.nq[k] = G[k].nq;
     A.wbase[k] = (int)wall.size();
     wall.insert(wall.end(), G[k].w.begin(), G[k].w.end());
@@ -237,24 +231,58 @@ int stls_error_norms(stls_handle h, const double* u, int nterms, const double* c
       gall.insert(gall.end(), gs, gs + 3 * (size_t)G[k].nq);
     }
   }
-  double *dw = nullptr, *dg = nullptr;
-  if ((rc = upload(&dw, wall, st))) return rc;
-  sc.ptrs.push_back(dw);
-  if ((rc = upload(&dg, gall, st))) return rc;
-  sc.ptrs.push_back(dg);
-  A.w = dw;
-  A.g = dg;
   // tensor sizes
   const int nt = h->dir[d].n;
   long long Gs = 1;
   for (int k = 0; k < d; ++k) Gs *= G[k].nq;
   const long long chunk = std::max<long long>(1, std::min<long long>(G[d].nq, kChunkPoints / Gs));
-  double *S = nullptr, *t0 = nullptr, *t1 = nullptr, *T = nullptr, *parts = nullptr;
-  if ((rc = sc.alloc(&S, (size_t)(Gs * nt)))) return rc;
-  if (d > 1 && (rc = sc.alloc(&t0, (size_t)(Gs * nt)))) return rc;
-  if (d > 2 && (rc = sc.alloc(&t1, (size_t)(Gs * nt)))) return rc;
-  if ((rc = sc.alloc(&T, (size_t)(Gs * chunk)))) return rc;
-  if ((rc = sc.alloc(&parts, 2 * (size_t)kNormBlocks))) return rc;
+  // device buffers, carved from the handle's workspace: sized by a dry run
+  double* dE[kMaxDim + 1];
+  int* dF[kMaxDim + 1];
+  double *dw, *dg, *S, *t0 = nullptr, *t1 = nullptr, *parts;
+  auto carve = [&](Arena& ar) {
+    for (int k = 0; k <= d; ++k) {
+      dE[k] = ar.take<double>(G[k].E.size());
+      dF[k] = ar.take<int>(G[k].first.size());
+    }
+    dw = ar.take<double>(wall.size());
+    dg = ar.take<double>(gall.size());
+    S = ar.take<double>((size_t)(Gs * nt));
+    if (d > 1) t0 = ar.take<double>((size_t)(Gs * nt));
+    if (d > 2) t1 = ar.take<double>((size_t)(Gs * nt));
+    parts = ar.take<double>(2 * (size_t)kNormBlocks);
+  };
+  Arena dry;
+  carve(dry);
+  if (h->norm_ws_bytes < dry.used) {
+    if (h->norm_ws) (void)hipFree(h->norm_ws);
+    h->norm_ws = nullptr;
+    h->norm_ws_bytes = 0;
+    if (hipMalloc((void**)&h->norm_ws, dry.used) != hipSuccess) {
+      h->norm_ws = nullptr;
+      set_error("hipMalloc (error norms workspace)");
+      return STLS_ENOMEM;
+    }
+    h->norm_ws_bytes = dry.used;
+  }
+  Arena ar;
+  ar.base = h->norm_ws;
+  carve(ar);
+  auto put = [&](void* dst, const void* src, size_t bytes) {
+    return bytes == 0 || hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess;
+  };
+  bool ok = true;
+  for (int k = 0; k <= d; ++k) {
+    ok = ok && put(dE[k], G[k].E.data(), G[k].E.size() * sizeof(double));
+    ok = ok && put(dF[k], G[k].first.data(), G[k].first.size() * sizeof(int));
+  }
+  ok = ok && put(dw, wall.data(), wall.size() * sizeof(double)) && put(dg, gall.data(), gall.size() * sizeof(double));
+  if (!ok) {
+    set_error("hipMemcpyAsync (error norms)");
+    return STLS_EHIP;
+  }
+  A.w = dw;
+  A.g = dg;
   std::vector<double> hp(2 * (size_t)kNormBlocks);
 
   // spatial chain: S (+)= u x_1 E_1^(ord[0]) ... x_d E_d^(ord[d-1])
@@ -285,11 +313,10 @@ int stls_error_norms(stls_handle h, const double* u, int nterms, const double* c
     for (long long q0 = 0; q0 < G[d].nq; q0 += chunk) {
       const int c = (int)std::min<long long>(chunk, G[d].nq - q0);
       const long long total = Gs * c;
-      hipLaunchKernelGGL(eval_mode_kernel, dim3(blocks_for(total)), dim3(kNT), 0, st, S, T, Gs, nt, c, 1LL,
-                         dE[d] + (size_t)tord * G[d].nq * G[d].np, dF[d], G[d].np, (int)q0, 0);
       A.q0 = (int)q0;
       const int nb = blocks_for(total);
-      hipLaunchKernelGGL(err_reduce_kernel, dim3(nb), dim3(kNT), 0, st, T, total, A, parts);
+      hipLaunchKernelGGL(err_reduce_kernel, dim3(nb), dim3(kNT), 0, st, S, Gs, nt, c,
+                         dE[d] + (size_t)tord * G[d].nq * G[d].np, dF[d], G[d].np, A, parts);
       if (hipGetLastError() != hipSuccess) { set_error("error-norm kernel launch"); return STLS_EHIP; }
       if (hipMemcpyAsync(hp.data(), parts, 2 * (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess) {
