@@ -120,46 +120,67 @@ __device__ inline double block_sum_n(double v, double* red) {
 // a chunk of time points, with F, the field on the grid, formed on the fly
 // from the space-evaluated S (shape (grid_s, n_t), grid_s = Gs):
 //   F(l, q) = sum_a Et[q0 + q][a] S(l, first_t[q0 + q] + a),
-// so the chunk never goes through memory.
-__global__ __launch_bounds__(kNT) void err_reduce_kernel(const double* __restrict__ S, long long Gs, int nt, int chunk,
+// so the chunk never goes through memory.  One thread per spatial point l
+// and run of kTimeSub time points walks the run: the point's decomposition,
+// spatial weight and the spatial factors of the exact solution
+// (kSpatialCache products at most; beyond that they are formed per point)
+// are computed once per run.
+constexpr int kSpatialCache = 8;
+constexpr int kTimeSub = 32;
+
+__global__ __launch_bounds__(kNT) void err_reduce_kernel(const double* __restrict__ S, int Gs, int nt, int chunk,
                                                          const double* __restrict__ Et, const int* __restrict__ first_t,
                                                          int np, NormArgs A, double* __restrict__ partials) {
   __shared__ double red[kNT / 64];
   double se = 0.0, sr = 0.0;
-  const long long total = Gs * chunk;
-  for (long long e = blockIdx.x * (long long)kNT + threadIdx.x; e < total; e += (long long)gridDim.x * kNT) {
-    const long long l = e % Gs;
-    const int qt = A.q0 + (int)(e / Gs);
-    double Fv = 0.0;
-    {
+  const int d = A.d, nfac = A.npat * A.nterms;
+  const int nsub = (chunk + kTimeSub - 1) / kTimeSub;
+  const long long items = (long long)Gs * nsub;
+  for (long long it = blockIdx.x * (long long)kNT + threadIdx.x; it < items; it += (long long)gridDim.x * kNT) {
+    const int l = (int)(it % Gs), qs = (int)(it / Gs) * kTimeSub;
+    int idx[kMaxDim] = {0, 0, 0};
+    int rest = l;
+#pragma unroll
+    for (int k = 0; k < kMaxDim; ++k) {
+      if (k >= d) break;
+      idx[k] = rest % A.nq[k];
+      rest /= A.nq[k];
+    }
+    double ws = 1.0;
+    for (int k = 0; k < d; ++k) ws *= A.w[A.wbase[k] + idx[k]];
+    // spatial factor of (pattern pt, term s): prod_{k<d} g_{s,k}^(pat[pt][k])(x_k)
+    auto spatial = [&](int pt, int s) {
+      double prod = 1.0;
+      for (int k = 0; k < d; ++k) prod *= A.g[A.gbase[k] + ((long long)s * 3 + A.pat[pt][k]) * A.nq[k] + idx[k]];
+      return prod;
+    };
+    double sp[kSpatialCache];
+#pragma unroll
+    for (int c = 0; c < kSpatialCache; ++c) sp[c] = c < nfac ? spatial(c / A.nterms, c % A.nterms) : 0.0;
+    for (int q = qs; q < min(chunk, qs + kTimeSub); ++q) {
+      const int qt = A.q0 + q;
+      double Fv = 0.0;
       const int f0 = first_t[qt];
       const double* row = Et + (size_t)qt * np;
       for (int a = 0; a < np; ++a) {
         const int j = f0 + a;
-        if (j >= 0 && j < nt) Fv += row[a] * S[l + (size_t)j * Gs];
+        if (j >= 0 && j < nt) Fv += row[a] * S[(size_t)l + (size_t)j * Gs];
       }
-    }
-    int idx[kMaxDim + 1];
-    long long rest = l;
+      double f = 0.0;
+      for (int c = 0; c < nfac; ++c) {
+        const int pt = c / A.nterms, s2 = c % A.nterms;
+        double spc = 0.0;
 #pragma unroll
-    for (int k = 0; k < kMaxDim; ++k) {
-      if (k >= A.d) break;
-      idx[k] = (int)(rest % A.nq[k]);
-      rest /= A.nq[k];
-    }
-    idx[A.d] = qt;
-    double wq = 1.0;
-    for (int k = 0; k <= A.d; ++k) wq *= A.w[A.wbase[k] + idx[k]];
-    double f = 0.0;
-    for (int pt = 0; pt < A.npat; ++pt)
-      for (int s = 0; s < A.nterms; ++s) {
-        double prod = 1.0;
-        for (int k = 0; k <= A.d; ++k) prod *= A.g[A.gbase[k] + ((long long)s * 3 + A.pat[pt][k]) * A.nq[k] + idx[k]];
-        f += prod;
+        for (int cc = 0; cc < kSpatialCache; ++cc)
+          if (cc == c) spc = sp[cc];
+        if (c >= kSpatialCache) spc = spatial(pt, s2);
+        f += spc * A.g[A.gbase[d] + ((long long)s2 * 3 + A.pat[pt][d]) * A.nq[d] + qt];
       }
-    const double diff = Fv - f;
-    se += wq * diff * diff;
-    sr += wq * f * f;
+      const double wq = ws * A.w[A.wbase[d] + qt];
+      const double diff = Fv - f;
+      se += wq * diff * diff;
+      sr += wq * f * f;
+    }
   }
   const double a = block_sum_n(se, red);
   const double b = block_sum_n(sr, red);
@@ -236,6 +257,7 @@ int stls_error_norms(stls_handle h, const double* u, int nterms, const double* c
   long long Gs = 1;
   for (int k = 0; k < d; ++k) Gs *= G[k].nq;
   const long long chunk = std::max<long long>(1, std::min<long long>(G[d].nq, kChunkPoints / Gs));
+  if (Gs >= (1LL << 31)) { set_error("error norms: too many spatial grid points"); return STLS_EINVAL; }
   // device buffers, carved from the handle's workspace: sized by a dry run
   double* dE[kMaxDim + 1];
   int* dF[kMaxDim + 1];
@@ -312,10 +334,9 @@ int stls_error_norms(stls_handle h, const double* u, int nterms, const double* c
     err = ref = 0.0;
     for (long long q0 = 0; q0 < G[d].nq; q0 += chunk) {
       const int c = (int)std::min<long long>(chunk, G[d].nq - q0);
-      const long long total = Gs * c;
       A.q0 = (int)q0;
-      const int nb = blocks_for(total);
-      hipLaunchKernelGGL(err_reduce_kernel, dim3(nb), dim3(kNT), 0, st, S, Gs, nt, c,
+      const int nb = blocks_for(Gs * ((c + kTimeSub - 1) / kTimeSub));
+      hipLaunchKernelGGL(err_reduce_kernel, dim3(nb), dim3(kNT), 0, st, S, (int)Gs, nt, c,
                          dE[d] + (size_t)tord * G[d].nq * G[d].np, dF[d], G[d].np, A, parts);
       if (hipGetLastError() != hipSuccess) { set_error("error-norm kernel launch"); return STLS_EHIP; }
       if (hipMemcpyAsync(hp.data(), parts, 2 * (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||

@@ -24,6 +24,12 @@ assembly on the device) and ``--solves`` PCG solves to 1e-8 with P^G and
 FP64 FD, right-hand side U[-1, 1] (seed 1):
 
     rocprofv3 --kernel-trace --stats -d OUT -o run -- python3 -m paper_1809_10026_amd.kernel_profile --mapped
+
+With ``--side`` it is, after the calibration copy, ``--solves`` general
+liftings (stls_lift_apply) at the benchmark shape (boundary coefficients
+U[-1, 1] on the 52^4 full space, seed 1814) and as many error-norm
+evaluations of the d = 2, p = 3, 64-element workload (a solution of a
+U[-1, 1] right-hand side, seed 1809, against sin(pi x) sin(pi y) sin(pi t)).
 """
 from __future__ import annotations
 
@@ -42,6 +48,7 @@ def main():
     ap.add_argument("--mode", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--batch", action="store_true", help="the 256-problem batched solve instead")
     ap.add_argument("--mapped", action="store_true", help="the rotated quarter annulus with P^G instead")
+    ap.add_argument("--side", action="store_true", help="general lifting and error norms instead")
     args = ap.parse_args()
     import torch
 
@@ -60,6 +67,8 @@ def main():
     del src, dst
     if args.mapped:
         return mapped(stls, torch, args.solves)
+    if args.side:
+        return side(stls, torch, args.solves)
 
     cfg = CONFIGS["d3_p4_nel48"]
     S = stls.Solver(*problem_knots(cfg["d"], cfg["n_el"], cfg["p"]))
@@ -97,6 +106,31 @@ def mapped(stls, torch, solves, n_sub=32, p=2):
         _, it, rel = S.solve(b, 1e-8, 3000, out=x)
         torch.cuda.synchronize()
         print(f"[kernel_profile] mapped solve {i}: {it} iterations, relres {rel:.2e}", flush=True)
+
+
+def side(stls, torch, reps):
+    import numpy as np
+
+    from stls_inputs import CONFIGS, problem_knots, uniform_pm1
+    cfg = CONFIGS["d3_p4_nel48"]
+    S = stls.Solver(*problem_knots(cfg["d"], cfg["n_el"], cfg["p"]))
+    ub = torch.as_tensor(uniform_pm1(S.forcing_shape[1], 1814)).cuda()
+    F = torch.zeros(S.ndof, dtype=torch.float64, device="cuda")
+    for i in range(reps):
+        S.lift_apply(ub, F)
+        torch.cuda.synchronize()
+        print(f"[kernel_profile] general lifting {i}", flush=True)
+    S.close()
+    c = CONFIGS["d2_p3_nel64"]
+    S = stls.Solver(*problem_knots(c["d"], c["n_el"], c["p"]))
+    b = torch.as_tensor(uniform_pm1(S.ndof, c["seed"])).cuda()
+    x, _, _ = S.solve(b, c["rtol"], 300)
+    pi = np.pi
+    fac = [[np.stack([np.sin(pi * q), pi * np.cos(pi * q), -pi * pi * np.sin(pi * q)])
+            for q in (S.norm_points(k)[0] for k in range(c["d"] + 1))]]
+    for i in range(reps):
+        r = S.error_norms(x, fac)
+        print(f"[kernel_profile] error norms {i}: {r}", flush=True)
 
 
 if __name__ == "__main__":

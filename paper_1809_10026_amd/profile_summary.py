@@ -37,6 +37,7 @@ CLASSES = [
     ("finalize_kernel", "reduce"),
     ("mapped_space_kernel", "mv_mapped_space"), ("mapped_time_kernel", "mv_mapped_time"),
     ("mapped_scale_kernel", "vec"), ("mapped_assemble_kernel", "setup"),
+    ("lift_class_kernel", "lift"), ("err_reduce_kernel", "norms"), ("eval_mode_kernel", "norms"),
 ]
 
 
