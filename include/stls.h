@@ -88,7 +88,7 @@ int stls_setup(int d, const int* nknots, const double* const* knots, const int* 
  * functions are the restricted tensor B-splines composed with G^{-1}.  The
  * system keeps the time Kronecker structure of §4.1 with sparse spatial
  * factors M_s = int B_i B_j, L_s = int grad B_i . grad B_j and
- * J_s = int Lap B_i Lap B_j over Omega, assembled on the host by Gauss
+ * J_s = int Lap B_i Lap B_j over Omega, assembled on the device by Gauss
  * quadrature with p + 3 points per non-empty span and applied as stencils.
  * ------------------------------------------------------------------------ */
 typedef enum stls_geometry {
@@ -116,8 +116,12 @@ typedef enum stls_mapped_prec {
  * stls_prec_apply (every FD precision), stls_pcg_solve, stls_set_kappa and
  * the profiling calls work as on the unit box; stls_set_fd_scaling(h, 1)
  * and the differentiation, lifting and error-norm calls return STLS_EINVAL.
- * Host work: the stencils cost O(ns (p+1)^(2d) (p+3)^d) and need at most
- * 2^26 quadrature points; synchronises the stream.  Errors as stls_setup.
+ * Setup work: the stencils are assembled on the device element by element
+ * (O(elements (p+1)^(2d) (p+3)^d) work, device memory 3 ns prod_k (2p_k+1)
+ * doubles); the geometry weights of P^G, their eigendecompositions and the
+ * scaling are formed on the host.  Synchronises the stream.  Errors as
+ * stls_setup, and STLS_EINVAL where the degree is too large for the
+ * matvec's LDS tile (p above 7 in 3-D).
  */
 int stls_setup_mapped(int d, const int* nknots, const double* const* knots, const int* degree, double kappa,
                       int geometry, int prec, void* stream, stls_handle* out);
@@ -214,9 +218,10 @@ int stls_norm_points(stls_handle h, int dir, double* x, double* w, int* nq);
  *          3*nq_k doubles: g_{s,k}, g_{s,k}' and g_{s,k}'' at the points of
  *          stls_norm_points(h, k, ...), in that order.
  *  out     host, 3 doubles.
- * Device temporaries (about 3 * prod_k nq_k(space) * n_t doubles) are
- * allocated for the call and freed before it returns; synchronises the
- * stream.  STLS_ENOMEM if they do not fit.
+ * Device temporaries (about 3 * prod_k nq_k(space) * n_t doubles and the
+ * tables) live in a workspace of the handle, allocated by the first call
+ * that needs it and grown when a later call needs more (freed by
+ * stls_destroy); synchronises the stream.  STLS_ENOMEM if they do not fit.
  */
 int stls_error_norms(stls_handle h, const double* u, int nterms, const double* const* g, double* out);
 
@@ -294,8 +299,12 @@ int stls_lift_combine(stls_handle h, const double* u0, const double* w, double* 
  * a(u, v) = int int (d_t u - kappa Lap u)(d_t v - kappa Lap v).
  * F -= a(u_B, B_i) for every restricted B_i; F: ndof doubles, in place.
  * On u_B of the zero-data space this equals the system matrix.  Entries of
- * u_B at restricted coefficients are included like any other.
- * STLS_EINVAL for NULL arguments. */
+ * u_B at restricted coefficients are included like any other.  Device
+ * temporaries: eight arrays of nfull doubles, allocated by the first call
+ * and kept in the handle.  STLS_EINVAL for NULL arguments, on a mapped
+ * domain, or where a direction's four bands exceed the 160 KB of LDS of
+ * one pass (n_k (2 p_k + 1) > 5120); STLS_ENOMEM if the temporaries do not
+ * fit. */
 int stls_lift_apply(stls_handle h, const double* ub, double* F);
 
 /* u = u_B + w placed at the restricted coefficients (restricted index i is
