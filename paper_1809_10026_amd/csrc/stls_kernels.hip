@@ -33,6 +33,7 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 256;
 constexpr int kCols = 64;          // FD panel width (columns per workgroup)
 constexpr int kLdx = kCols + 16;   // LDS row stride of a panel: rows fill distinct banks
+constexpr int kStageBatch = 4;     // operator pieces per thread in flight while staging
 constexpr int kMaxBlocksEW = 8192; // grid cap of grid-stride elementwise kernels
 
 // ---------------------------------------------------------------------------
@@ -121,16 +122,28 @@ __global__ __launch_bounds__(kThreads) void fd_mode_kernel(
   const int krow = lane >> 4;
   double dsum = 0.0;
 
-  if (WLDS)
-    for (int e = tid; e < NPAD * NPAD; e += kThreads) {
-      const int j = e / NPAD, i = e - j * NPAD;
-      Ws[j * LDW + i] = Aop[e];
+  // operators into LDS in pairs of entries, kStageBatch pairs per thread
+  // with their loads in flight before the stores
+  auto stage_w = [&](const TC* __restrict__ src, TC* dst) {
+    typedef TC pair_t __attribute__((ext_vector_type(2)));
+    constexpr int P2 = NPAD / 2, TOT = NPAD * P2;
+    for (int e0 = tid; e0 < TOT; e0 += kThreads * kStageBatch) {
+      pair_t v[kStageBatch];
+#pragma unroll
+      for (int b = 0; b < kStageBatch; ++b)
+        v[b] = *reinterpret_cast<const pair_t*>(src + (size_t)min(e0 + b * kThreads, TOT - 1) * 2);
+#pragma unroll
+      for (int b = 0; b < kStageBatch; ++b) {
+        const int e = e0 + b * kThreads;
+        if (e < TOT) {
+          const int j = e / P2, i2 = e - j * P2;
+          *reinterpret_cast<pair_t*>(dst + j * LDW + 2 * i2) = v[b];
+        }
+      }
     }
-  if (FUSED && w2lds)
-    for (int e = tid; e < NPAD * NPAD; e += kThreads) {
-      const int j = e / NPAD, i = e - j * NPAD;
-      Ws2[j * LDW + i] = Aop2[e];
-    }
+  };
+  if (WLDS) stage_w(Aop, Ws);
+  if (FUSED && w2lds) stage_w(Aop2, Ws2);
   // eigenvalues of this thread's output rows (rows are fixed per lane)
   double lt[FUSED ? NM * 4 : 1];
   if constexpr (FUSED) {
@@ -399,13 +412,29 @@ __global__ __launch_bounds__(kThreads) void fd_mode_bf16x3_kernel(
   const int ccol = wave * 16 + (lane & 15);
   double dsum = 0.0;
 
+  // operator rows into LDS in 16-byte pieces (8 bf16), kStageBatch pieces
+  // per thread with their loads in flight before the stores
   auto stage_w = [&](const unsigned short* __restrict__ h, const unsigned short* __restrict__ l, int slot) {
     unsigned short* dh = Ws + slot * 2 * NPAD * LDK;
     unsigned short* dl = dh + NPAD * LDK;
-    for (int e = tid; e < NPAD * KPAD; e += kThreads) {
-      const int i = e / KPAD, kk = e - i * KPAD;
-      dh[i * LDK + kk] = h[e];
-      dl[i * LDK + kk] = l[e];
+    constexpr int P8 = KPAD / 8, TOT = NPAD * P8;
+    for (int e0 = tid; e0 < TOT; e0 += kThreads * kStageBatch) {
+      us8_t vh[kStageBatch], vl[kStageBatch];
+#pragma unroll
+      for (int b = 0; b < kStageBatch; ++b) {
+        const int e = min(e0 + b * kThreads, TOT - 1);
+        vh[b] = *reinterpret_cast<const us8_t*>(h + (size_t)e * 8);
+        vl[b] = *reinterpret_cast<const us8_t*>(l + (size_t)e * 8);
+      }
+#pragma unroll
+      for (int b = 0; b < kStageBatch; ++b) {
+        const int e = e0 + b * kThreads;
+        if (e < TOT) {
+          const int i = e / P8, k8 = e - i * P8;
+          *reinterpret_cast<us8_t*>(dh + i * LDK + k8 * 8) = vh[b];
+          *reinterpret_cast<us8_t*>(dl + i * LDK + k8 * 8) = vl[b];
+        }
+      }
     }
   };
   stage_w(Wh, Wl, 0);
