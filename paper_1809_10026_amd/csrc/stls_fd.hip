@@ -218,6 +218,30 @@ constexpr size_t slab_lds_bytes(int NM) {
          ((slab_op1_in_lds<PR>() ? 1 : 2) * 64 * kSlabLdy + (slab_op1_in_lds<PR>() ? 16 * NM * (32 * ((NM + 1) / 2) + 8) : 0));
 }
 
+// rows x KPAD operator entries (row-major, rows of KPAD) into LDS rows of
+// stride LDV: 16-byte pieces, four per thread with their loads in flight
+// before the stores (an element per iteration would wait for every load).
+template <typename SD, int KPAD, int LDV>
+__device__ __forceinline__ void stage_rows(const SD* __restrict__ src, SD* dst, int rows) {
+  constexpr int PE = 16 / (int)sizeof(SD), PR = KPAD / PE;
+  static_assert(KPAD % PE == 0 && (LDV * (int)sizeof(SD)) % 16 == 0, "16-byte pieces");
+  typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
+  const int tot = rows * PR;
+  for (int e0 = threadIdx.x; e0 < tot; e0 += blockDim.x * 4) {
+    u4_t v[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int e = min(e0 + b * (int)blockDim.x, tot - 1);
+      v[b] = *reinterpret_cast<const u4_t*>(src + (size_t)(e / PR) * KPAD + (e % PR) * PE);
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int e = e0 + b * (int)blockDim.x;
+      if (e < tot) *reinterpret_cast<u4_t*>(dst + (e / PR) * LDV + (e % PR) * PE) = v[b];
+    }
+  }
+}
+
 template <int PR, int NM, bool FWD, bool DOT, bool SCALE>
 __global__ __launch_bounds__(256) void fd_slab_kernel(
     const typename std::conditional<FWD, double, typename Prec<PR>::T>::type* __restrict__ X,
@@ -258,10 +282,7 @@ __global__ __launch_bounds__(256) void fd_slab_kernel(
   const int g = lane >> 4, cl = lane & 15;
   Frag b1[W1L ? 1 : NM][NK], a2[NK];
   if constexpr (W1L) {
-    for (int e = threadIdx.x; e < NP * KPAD; e += 256) {
-      const int i = e / KPAD, k = e - i * KPAD;
-      w1s[i * LDV + k] = W1h[e];
-    }
+    stage_rows<SD, KPAD, LDV>(W1h, w1s, NP);
     __syncthreads();
   }
 #pragma unroll
@@ -451,16 +472,13 @@ __global__ __launch_bounds__(kStridedWaves * 64, (strided_min_blocks<PR, FUSED, 
   if constexpr (FUSED || WL) {
     if constexpr (FUSED)
       for (int i = threadIdx.x; i < 16 * NM; i += blockDim.x) lt_lds[i] = lam_t[min(i, n - 1)];
-    for (int e = threadIdx.x; e < 16 * NM * KPAD; e += blockDim.x) {
-      const int i = e / KPAD, k = e - i * KPAD;
-      if constexpr (FUSED) {
-        v2h[i * LDV + k] = W2h[e];
-        if constexpr (P::kHalves == 2) v2l[i * LDV + k] = W2l[e];
-      }
-      if constexpr (WL) {
-        w1h[i * LDV + k] = Wh[e];
-        if constexpr (P::kHalves == 2) w1l[i * LDV + k] = Wl[e];
-      }
+    if constexpr (FUSED) {
+      stage_rows<SD, KPAD, LDV>(W2h, v2h, 16 * NM);
+      if constexpr (P::kHalves == 2) stage_rows<SD, KPAD, LDV>(W2l, v2l, 16 * NM);
+    }
+    if constexpr (WL) {
+      stage_rows<SD, KPAD, LDV>(Wh, w1h, 16 * NM);
+      if constexpr (P::kHalves == 2) stage_rows<SD, KPAD, LDV>(Wl, w1l, 16 * NM);
     }
     __syncthreads();
   }
