@@ -124,3 +124,18 @@ def test_error_norms_reject_bad_arguments():
     x = to_dev(np.zeros(S.ndof))
     with pytest.raises(_lib().StlsError):
         S.error_norms(x, [])
+
+
+def test_workspace_reuse_matches_a_fresh_handle():
+    """The norms' tables and temporaries live in a workspace of the handle
+    that grows when a call needs more: one term, then three terms (a larger
+    table), then one term again on the same handle give exactly the results
+    of fresh handles."""
+    S, knots, degs, x = _solve_manufactured(2, 6, 3)
+    pts = [S.norm_points(k)[0] for k in range(3)]
+    one = [[_sin_factors(p) for p in pts]]
+    three = one + [[_sin_factors(p, 2.0) for p in pts], [_t2_factors(p) for p in pts]]
+    seq = [S.error_norms(x, one), S.error_norms(x, three), S.error_norms(x, one)]
+    for terms, got in zip((one, three, one), seq):
+        ref = _lib().Solver(knots, degs).error_norms(x, terms)
+        assert got == ref, (got, ref)
