@@ -1747,6 +1747,23 @@ __global__ __launch_bounds__(kThreads) void dot_kernel(const double* __restrict_
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// This thread's share of a fixed-order sum of partials: entries tid,
+// tid + stride, tid + 2 stride, ... added in that order, with the loads of
+// eight entries issued before their additions.
+__device__ inline double strided_sum(const double* __restrict__ partials, int nparts, int tid, int stride) {
+  double v = 0.0;
+  int i = tid;
+  for (; i + 7 * stride < nparts; i += 8 * stride) {
+    double b[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) b[k] = partials[i + k * stride];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v += b[k];
+  }
+  for (; i < nparts; i += stride) v += partials[i];
+  return v;
+}
+
 enum FinKind { FIN_BNORM = 0, FIN_RHO0, FIN_ALPHA, FIN_RR, FIN_BETA };
 
 // One workgroup sums the partials in a fixed order and updates the scalars.
@@ -1755,9 +1772,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(const double* __rest
                                                             double* __restrict__ hist, int it) {
   __shared__ double red[4];
   if (S->done || S->flag) return;
-  double v = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kThreads) v += partials[i];
-  const double s = block_sum(v, red);
+  const double s = block_sum(strided_sum(partials, nparts, threadIdx.x, kThreads), red);
   if (threadIdx.x != 0) return;
   switch (kind) {
     case FIN_BNORM:
@@ -1797,8 +1812,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(const double* __rest
 
 // Sum of nparts partial sums in a fixed order (identical in every block).
 __device__ inline double sum_partials(const double* __restrict__ partials, int nparts, double* red) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += partials[i];
+  double v = strided_sum(partials, nparts, threadIdx.x, blockDim.x);
   v = block_sum(v, red);
   __syncthreads();
   if (threadIdx.x == 0) red[0] = v;
