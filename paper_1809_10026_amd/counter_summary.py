@@ -43,7 +43,7 @@ def mfma(args):
     prec = MODE_PREC[args.mode]
     per = read_counters(args.mfma)
     dur = {r["Name"]: float(r["AverageNs"]) for r in read_stats(args.trace)} if args.trace else {}
-    out = [f"# MFMA activity: {args.title}", "", "Commands (repository root on the GPU box):", ""]
+    out = [f"# MFMA activity: {args.title}", "", "Commands (run from the repository root):", ""]
     out += ["    " + c for c in args.command.split(";")]
     out += ["", f"Flops = SQ_INSTS_VALU_MFMA_MOPS_{prec} x 512 per dispatch; duration = mean from the kernel trace; "
             f"peak = MI355X dense {prec} MFMA, {PEAK_TF[prec]} TFLOP/s.  Busy = sum(SQ_VALU_MFMA_BUSY_CYCLES) / "
@@ -66,7 +66,7 @@ def mfma(args):
 
 def waits(args):
     per = read_counters(args.waits)
-    out = [f"# Wave cycles: {args.title}", "", "Commands (repository root on the GPU box):", ""]
+    out = [f"# Wave cycles: {args.title}", "", "Commands (run from the repository root):", ""]
     out += ["    " + c for c in args.command.split(";")]
     out += ["", "Shares of SQ_WAVE_CYCLES (summed over the waves of a dispatch, same units): waiting on anything "
             "(memory or dependencies), waiting to issue, issuing any instruction, issuing VALU, issuing LDS.", "",

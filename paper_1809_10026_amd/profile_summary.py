@@ -108,7 +108,7 @@ def main():
 
     rows = read_stats(args.stats)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    out = [f"# {args.title}", "", "Commands (repository root on the GPU box):", ""]
+    out = [f"# {args.title}", "", "Commands (run from the repository root):", ""]
     out += ["    " + c for c in args.command.split(";")]
     out += ["", "Durations from `run_kernel_stats.csv` (ns).", "",
             "| kernel | class | calls | avg ns | min ns | max ns | total % |", "|---|---|---|---|---|---|---|"]
